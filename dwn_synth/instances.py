@@ -1,0 +1,153 @@
+"""Complete problem instances: system + scenario tree + node demands + initial
+conditions (paper eq. demand:tree, eq. Sc-MPC).
+
+Workload recipes (all seeded, all synthetic):
+
+* ``tiny_instance``: 4 tanks / 3 flows / 2 demands, ``N = 4``, branching
+  [2, 2] (4 scenarios, 11 nodes), demands ``N(1.0, 0.1^2)`` per node and
+  component, ``p = 5``, ``q = 1``.
+* ``barcelona_instance``: Barcelona-shaped system (63/114/88/17), ``N = 24``,
+  branching [7, 7, 7] (343 scenarios, 7260 nodes), log-normal demands around
+  a 24-periodic profile with 10 % spread, feasible junction demands, hourly
+  pumping tariff.
+* ``batch_instances``: 64 trees (seeds 100..163) on the Barcelona-shaped
+  system, horizons in {12, 18, 24}, scenario counts in {16, 64, 125, 343, 512}.
+* ``random_small_instance``: small dense systems with general ``A`` and
+  couplings, for exact-arithmetic checks.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .systems import barcelona_shaped_system, random_dense_system, tiny_tank_system
+from .trees import uniform_tree
+
+
+@dataclass
+class Instance:
+    """One scenario-tree MPC problem.  ``d`` is ``(M, nd)``, ``alpha2`` is
+    ``(N, nu)``, ``p`` the measured state, ``q`` the previous input."""
+
+    name: str
+    sys: dict
+    tree: dict
+    d: np.ndarray
+    alpha2: np.ndarray
+    p: np.ndarray
+    q: np.ndarray
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def M(self) -> int:
+        return int(self.tree["M"])
+
+    @property
+    def N(self) -> int:
+        return int(self.tree["N"])
+
+
+def tiny_instance(seed: int = 0, N: int = 4, branching=(2, 2)) -> Instance:
+    sys = tiny_tank_system(seed)
+    tree = uniform_tree(N, list(branching))
+    rng = np.random.default_rng([seed, 1])
+    d = rng.normal(1.0, 0.1, size=(tree["M"], sys["nd"]))
+    alpha2 = np.zeros((N, sys["nu"]))
+    return Instance("tiny", sys, tree, d, alpha2, np.full(sys["nx"], 5.0), np.ones(sys["nu"]))
+
+
+def tariff(hour: int) -> float:
+    """Two-level electricity tariff: peak 1.0 for hours 8..21, off-peak 0.4."""
+    return 1.0 if 8 <= (hour % 24) < 22 else 0.4
+
+
+def pumping_cost(sys: dict, N: int, start_hour: int = 0) -> np.ndarray:
+    """Time-varying pumping cost ``alpha_2`` (N, nu): tariff x pump weight."""
+    a2 = np.zeros((N, sys["nu"]))
+    for j in range(N):
+        a2[j, sys["pump_cols"]] = tariff(start_hour + j) * sys["pump_weight"]
+    return a2
+
+
+def barcelona_demands(sys: dict, tree: dict, rng: np.random.Generator, start_hour: int = 0):
+    """Node demands for a Barcelona-shaped system.
+
+    Tank demands: ``dhat_k(j) = b_k (1 + 0.3 sin(2 pi (j + phi_k) / 24))`` with
+    ``b_k ~ U[0.5, 2]``, ``phi_k ~ U[0, 24)``, perturbed per node by the
+    log-normal factor ``exp(0.1 eps - 0.005)``, ``eps ~ N(0, 1)``.
+    Junction demands are set to ``E u_f`` for a per-node flow ``u_f`` sampled
+    in the inner 80 % of the input box, so every node's coupling
+    ``E u + Ed d = 0`` has a solution inside the box.
+    Returns ``(d, u_f)``.
+    """
+    M, ne, nd = tree["M"], sys["ne"], sys["nd"]
+    nt = nd - ne
+    b = rng.uniform(0.5, 2.0, nt)
+    phi = rng.uniform(0.0, 24.0, nt)
+    hours = (start_hour + tree["stage"]).astype(np.float64)
+    dhat = b[None, :] * (1.0 + 0.3 * np.sin(2.0 * np.pi * (hours[:, None] + phi[None, :]) / 24.0))
+    eps = rng.standard_normal((M, nt))
+    d = np.zeros((M, nd))
+    d[:, ne:] = dhat * np.exp(0.1 * eps - 0.005)
+    span = sys["umax"] - sys["umin"]
+    uf = rng.uniform(sys["umin"] + 0.1 * span, sys["umax"] - 0.1 * span, size=(M, sys["nu"]))
+    d[:, :ne] = uf @ sys["E"].T
+    return d, uf
+
+
+def barcelona_instance(seed: int = 1, N: int = 24, branching=(7, 7, 7), sys: dict | None = None,
+                       demand_seed: int | None = None) -> Instance:
+    if sys is None:
+        sys = barcelona_shaped_system(seed)
+    tree = uniform_tree(N, list(branching))
+    rng = np.random.default_rng([seed if demand_seed is None else demand_seed, 2])
+    d, uf = barcelona_demands(sys, tree, rng)
+    alpha2 = pumping_cost(sys, N)
+    p = 0.6 * sys["xmax"]
+    q = uf.mean(axis=0)
+    return Instance(f"barcelona-N{N}-b{'x'.join(map(str, branching))}", sys, tree, d, alpha2, p, q,
+                    extra={"uf": uf})
+
+
+BATCH_SHAPES = {16: [4, 4], 64: [4, 4, 4], 125: [5, 5, 5], 343: [7, 7, 7], 512: [8, 8, 8]}
+BATCH_HORIZONS = (12, 18, 24)
+
+
+def batch_instances(n_trees: int = 64, first_seed: int = 100, system_seed: int = 1) -> list[Instance]:
+    """``n_trees`` independent trees on one shared Barcelona-shaped system.
+
+    Tree ``i`` uses seed ``first_seed + i`` to draw its horizon (uniform in
+    {12, 18, 24}), its scenario count (uniform in {16, 64, 125, 343, 512},
+    full branching over the first 2-3 stages), its demands and its initial
+    tank levels ``p = x_max * U(0.4, 0.8)``.
+    """
+    sys = barcelona_shaped_system(system_seed)
+    out = []
+    for i in range(n_trees):
+        seed = first_seed + i
+        rng = np.random.default_rng(seed)
+        N = int(rng.choice(BATCH_HORIZONS))
+        scen = int(rng.choice(sorted(BATCH_SHAPES)))
+        branching = BATCH_SHAPES[scen]
+        tree = uniform_tree(N, branching)
+        d, uf = barcelona_demands(sys, tree, rng)
+        alpha2 = pumping_cost(sys, N)
+        p = sys["xmax"] * rng.uniform(0.4, 0.8, sys["nx"])
+        q = uf.mean(axis=0)
+        out.append(Instance(f"batch{seed}-N{N}-s{scen}", sys, tree, d, alpha2, p, q, extra={"uf": uf}))
+    return out
+
+
+def random_small_instance(seed: int, nx: int = 4, nu: int = 5, nd: int = 3, ne: int = 2,
+                          N: int = 3, branching=(2, 2), scenarios: int | None = None) -> Instance:
+    """Dense random system (general ``A``, ``ne`` couplings) on a small tree."""
+    sys = random_dense_system(seed, nx, nu, nd, ne)
+    tree = uniform_tree(N, list(branching), scenarios=scenarios)
+    rng = np.random.default_rng([seed, 3])
+    d = rng.standard_normal((tree["M"], nd))
+    alpha2 = 0.5 * rng.standard_normal((N, nu))
+    p = rng.uniform(0.0, 2.0, nx)
+    q = rng.uniform(-1.0, 1.0, nu)
+    return Instance(f"random{seed}", sys, tree, d, alpha2, p, q)

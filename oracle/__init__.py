@@ -1,0 +1,40 @@
+"""FP64 CPU oracle of the accelerated dual proximal gradient (APG) solver for
+scenario-tree stochastic MPC (Sampathirao, Sopasakis, Bemporad, Patrinos,
+"GPU-accelerated stochastic predictive control of drinking water networks").
+
+TEST INFRASTRUCTURE ONLY.  It exists to check the GPU library.  Only the test
+suite, the smoke check and the benchmark's CPU-baseline leg may import it; the
+library never calls it, and it shares no code with the library.
+"""
+
+from .smpc_oracle import (
+    OracleProblem,
+    null_space_basis,
+    cost_update,
+    factor_step,
+    solve_step,
+    prox_dist,
+    prox_g,
+    theta_next,
+    theta_sequence,
+    apg,
+    primal_cost,
+    dual_hessian_dense,
+    dual_lmax_power,
+)
+
+__all__ = [
+    "OracleProblem",
+    "null_space_basis",
+    "cost_update",
+    "factor_step",
+    "solve_step",
+    "prox_dist",
+    "prox_g",
+    "theta_next",
+    "theta_sequence",
+    "apg",
+    "primal_cost",
+    "dual_hessian_dense",
+    "dual_lmax_power",
+]
