@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of the APG solver for scenario-tree SMPC on one MI355X.
+
+Default workload: the Barcelona-shaped plain method in float64 -- 63 tanks,
+114 flows, 88 demands, 17 junctions, horizon N = 24, branching 7 at the first
+three stages (343 scenarios, 7260 decision nodes), log-normal demands around a
+24-periodic profile, cold start, tolerance 1e-3.  One step = one solve to
+tolerance; `value` is APG iterations per second over the timed steps (inputs
+resident in HBM; each solve uploads p and the root term, ~1.4 kB, and reads
+back u0).
+
+A second leg solves 64 trees of uneven size (horizons 12/18/24, 16..512
+scenarios, ~260k nodes) in one batch with the float32 bulk + float64 polish
+recipe and reports its solves/s and iterations/s beside the float64 number.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "APG iters/s + solves/s to tol 1e-3 (FP32 batched vs FP64 plain); p50/p99 latency"
+
+
+def node_bytes(kernel: str, nx: int, nu: int, elem: int, scaled: bool) -> int:
+    """Compulsory bytes per node of one kernel launch (each input read once,
+    each output written once)."""
+    D = 2 * nx + nu
+    sc = 3 if scaled else 0
+    if kernel.startswith("backward"):
+        # y^nu, y^{nu-1}, beta, pi, scale -> du
+        return elem * (2 * D + nu + 1 + sc + nu)
+    if kernel.startswith("forward"):
+        # du, uhat, e, pi, scale, y^nu, y^{nu-1} -> y^{nu+1}
+        return elem * (2 * nu + nx + 1 + sc + 2 * D + D)
+    return 0
+
+
+def iteration_bytes(nx: int, nu: int, elem: int, scaled: bool) -> int:
+    """Minimum bytes one APG iteration must move per node: the dual iterates
+    y^nu, y^{nu-1} read and y^{nu+1} written once, the node data beta, uhat,
+    e, pi (and the scaling) read once."""
+    D = 2 * nx + nu
+    return elem * (3 * D + 2 * nu + nx + 1 + (3 if scaled else 0))
+
+
+def cpu_baseline(inst, seconds: float, precond_scale, lam) -> dict:
+    import oracle as O
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    P = O.OracleProblem.from_instance(inst)
+    F = O.factor_step(P)
+    t0 = time.perf_counter()
+    O.apg(P, lam, 2, F, scale=precond_scale)
+    per = (time.perf_counter() - t0) / 2
+    iters = max(2, int(seconds / max(per, 1e-6)))
+    t0 = time.perf_counter()
+    O.apg(P, lam, iters, F, scale=precond_scale)
+    dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "APG iterations/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{iters} FP64 iterations of the 7260-node Barcelona-shaped tree (no stop test)",
+            "seconds": dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch-steps", type=int, default=1)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the solver runs on a single MI355X and has no multi-GPU path "
+              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import dwn_synth as ds
+    from paper_1604_01074_amd import solver
+
+    torch.cuda.set_device(0)
+    inst = ds.barcelona_instance()
+    nx, nu = inst.sys["nx"], inst.sys["nu"]
+    ctx = solver.Context(0)
+    system, tree = solver.from_instance(ctx, inst, precond=1, power_iters=200)
+    lam, S = tree.factor_info(with_scale=True)
+    info = tree.info()
+    opts = dict(tol=1e-3, max_iter=20000, check_every=10, precision=64, want_x=False, want_y=False)
+    print(f"[bench] plain FP64: M={inst.M} chains={info['n_chains']} levels={info['n_levels']} lambda={lam:.4e}",
+          file=sys.stderr, flush=True)
+    for _ in range(a.warmup):
+        tree.solve(inst.p, inst.q, **opts)
+    torch.cuda.synchronize()
+    lat, iters = [], []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        s0 = time.perf_counter()
+        r = tree.solve(inst.p, inst.q, **opts)
+        lat.append(time.perf_counter() - s0)
+        iters.append(r["iterations"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = sum(iters) / elapsed
+    print(f"[bench] plain FP64: {a.steps} solves, {iters[0]} iterations each, {elapsed:.3f} s, "
+          f"{value:.1f} it/s, status {r['status']} r_p {r['r_primal']:.3e}", file=sys.stderr, flush=True)
+
+    # same steps again with per-kernel HIP events for the roofline
+    ctx.reset_stats()
+    ctx.profiling(True)
+    for _ in range(a.steps):
+        tree.solve(inst.p, inst.q, **opts)
+    stats = ctx.kernel_stats()
+    ctx.profiling(False)
+    dom = max(stats, key=lambda k: stats[k]["total_ms"])
+    avg_ms = stats[dom]["total_ms"] / stats[dom]["launches"]
+    # nodes one launch of the dominant kernel covers
+    leaf = dom.split("_")[1] == "leaf"
+    nodes_per_launch = _level_nodes(inst.tree, leaf)
+    per_node = node_bytes(dom, nx, nu, 8, True)
+    achieved = per_node * nodes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": per_node * nodes_per_launch}
+    kernels = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["total_ms"] / v["launches"], 2),
+                   "share": round(v["total_ms"] / sum(x["total_ms"] for x in stats.values()), 3)}
+               for k, v in stats.items()}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "APG iterations/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(1e3 * elapsed / a.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Barcelona-shaped plain method, FP64: nx=63 nu=114 nd=88 ne=17, N=24, "
+                               "branching [7,7,7] (343 scenarios, 7260 nodes), tol 1e-3, cold start",
+                   "nodes": inst.M, "tol": 1e-3, "check_every": 10, "precond": "single-branch diagonal"},
+        "solves_per_s": round(a.steps / elapsed, 3),
+        "iterations_per_solve": iters[0],
+        "node_iterations_per_s": round(value * inst.M, 1),
+        "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
+        "iteration_bytes_per_node": iteration_bytes(nx, nu, 8, True),
+        "achieved_iteration_GBs": round(iteration_bytes(nx, nu, 8, True) * inst.M * value / 1e9, 1),
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+
+    if not a.no_batch:
+        out["batched_fp32"] = batched_leg(ctx, a.batch_steps)
+
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds, S, lam)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _level_nodes(tree: dict, leaf: bool) -> int:
+    """Nodes covered by the leaf-chain (after the last branching) or the
+    inner levels of a tree."""
+    par = np.asarray(tree["parent"])
+    M = tree["M"]
+    nch = np.bincount(par[par >= 0], minlength=M)
+    # a node belongs to a leaf chain when no node on its path below branches
+    below_branch = np.zeros(M, dtype=bool)
+    for n in range(M - 1, -1, -1):
+        if nch[n] >= 2:
+            below_branch[n] = True
+        if par[n] >= 0 and below_branch[n]:
+            below_branch[par[n]] = True
+    leaf_nodes = int((~below_branch).sum())
+    return leaf_nodes if leaf else M - leaf_nodes
+
+
+def batched_leg(ctx, steps: int) -> dict:
+    import torch
+
+    import dwn_synth as ds
+
+    insts = ds.batch_instances(64)
+    system = ctx.system(insts[0].sys)
+    trees = []
+    t0 = time.perf_counter()
+    for inst in insts:
+        t = system.tree(inst.tree)
+        t.set_data(inst.d, inst.alpha2)
+        t.factor(precond=1, power_iters=100)
+        trees.append(t)
+    setup_s = time.perf_counter() - t0
+    nodes = sum(i.M for i in insts)
+    kw = dict(tol=1e-3, max_iter=20000, check_every=10, precision=32, polish_iters=20, want_x=False, want_y=False)
+    ps = [i.p for i in insts]
+    qs = [i.q for i in insts]
+    system.solve_batch(trees, ps, qs, **kw)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        code, res = system.solve_batch(trees, ps, qs, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tree_iters = sum(r["iterations"] for r in res) * steps
+    node_iters = sum(r["iterations"] * i.M for r, i in zip(res, insts)) * steps
+    out = {"trees": len(insts), "nodes": nodes, "solves_per_s": round(len(insts) * steps / dt, 2),
+           "tree_iterations_per_s": round(tree_iters / dt, 1),
+           "node_iterations_per_s": round(node_iters / dt, 1),
+           "ms_per_batch": round(1e3 * dt / steps, 2),
+           "iterations_max": max(r["iterations"] for r in res),
+           "iterations_median": float(np.median([r["iterations"] for r in res])),
+           "fp32_iterations_median": float(np.median([r["fp32_iterations"] for r in res])),
+           "status_worst": int(code), "setup_s": round(setup_s, 2), "dtype": "f32 bulk + 20 f64 polish"}
+    system.close()
+    ctx.systems.remove(system)
+    return out
+
+
+if __name__ == "__main__":
+    sys.exit(main())

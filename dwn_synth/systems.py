@@ -59,35 +59,63 @@ N_PUMPS = 38
 
 
 def barcelona_shaped_system(seed: int = 1) -> dict:
-    """A random network with the Barcelona DWN dimensions (Sec. V).
+    """A random flow network with the Barcelona DWN dimensions (Sec. V).
 
-    63 tanks, 114 flows, 88 demands, 17 junctions.  ``A = I``.  ``B`` has 2-4
-    (+-1) entries per column with at least one +1 and one -1.  ``E`` has 17
-    junction rows with 4-8 (+-1) flows each, resampled until it has full row
-    rank.  The first 17 demands are junction demands (``Ed = -[I 0]``); the
-    other 71 drain tanks (``Gd = -selector``, every tank drained at least once).
-    Tanks ``x in [0, 20 + U(0,30)]`` (soft), safety level ``0.3 x_max``; flows
-    ``u in [0, U(2,10)]``.  ``alpha1 ~ U[0.5, 2]``; 38 flows are pumps whose
+    63 tanks, 114 flows, 88 demands, 17 junctions, ``A = I``.  Every flow
+    carries water from an origin (a source such as a treatment plant or well, a
+    tank, or a junction) to a destination (a tank or a junction):
+    ``B[dest_tank, j] = +1``, ``B[orig_tank, j] = -1``, and a junction row of
+    ``E`` has +1 for its inflows and -1 for its outflows, so
+    ``E u + Ed d = 0`` with ``Ed = -[I 0]`` is the junction mass balance
+    (first 17 demands).  The flows are: 17 x 3 junction flows (one inflow, from
+    a source for 6 junctions and from a tank for 11, and two outflows to
+    tanks), 14 sources feeding tanks directly and 49 tank-to-tank transfers;
+    every tank receives at least one inflow.  The other 71 demands drain tanks
+    (``Gd = -selector``, every tank drained at least once).
+    Tanks ``x in [0, 20 + U(0,30)]`` (soft), safety level ``0.3 x_max``;
+    flows ``u in [0, u_max]``, ``u_max ~ U[4, 12]`` for sources and
+    ``U[2, 10]`` otherwise.  ``alpha1 ~ U[0.5, 2]``; 38 flows are pumps whose
     time-varying cost weight is stored as ``pump_cols``/``pump_weight``.
     Weights keep the paper's ratios (``W_u = 5 I, W_x = 500, gamma_d = 2500``).
     """
     rng = np.random.default_rng(seed)
     nx, nu, nd, ne = 63, 114, 88, 17
+    # (origin kind, destination kind): kinds are "src", "tank", "junc"
+    flows = []
+    for r in range(ne):
+        flows.append(("src" if r < 6 else "tank", ("junc", r)))
+        flows.append((("junc", r), "tank"))
+        flows.append((("junc", r), "tank"))
+    flows += [("src", "tank")] * 14
+    flows += [("tank", "tank")] * (nu - len(flows))
+    assert len(flows) == nu
+    order = rng.permutation(nu)
+    flows = [flows[k] for k in order]
+    n_dest_tank = sum(1 for f in flows if f[1] == "tank")
+    dest_tanks = np.concatenate([rng.permutation(nx), rng.integers(0, nx, size=n_dest_tank - nx)])
+    rng.shuffle(dest_tanks)
     B = np.zeros((nx, nu))
-    for j in range(nu):
-        k = int(rng.integers(2, 5))
-        rows = rng.choice(nx, size=k, replace=False)
-        signs = rng.choice([-1.0, 1.0], size=k)
-        signs[0], signs[1] = 1.0, -1.0
-        B[rows, j] = signs
-    while True:
-        E = np.zeros((ne, nu))
-        for r in range(ne):
-            k = int(rng.integers(4, 9))
-            cols = rng.choice(nu, size=k, replace=False)
-            E[r, cols] = rng.choice([-1.0, 1.0], size=k)
-        if np.linalg.matrix_rank(E) == ne:
-            break
+    E = np.zeros((ne, nu))
+    is_src = np.zeros(nu, dtype=bool)
+    k = 0
+    for j, (orig, dest) in enumerate(flows):
+        if dest == "tank":
+            dt = int(dest_tanks[k])
+            k += 1
+            B[dt, j] = 1.0
+        else:
+            dt = -1
+            E[dest[1], j] = 1.0
+        if orig == "src":
+            is_src[j] = True
+        elif orig == "tank":
+            ot = int(rng.integers(0, nx))
+            while ot == dt:
+                ot = int(rng.integers(0, nx))
+            B[ot, j] = -1.0
+        else:
+            E[orig[1], j] = -1.0
+    assert np.linalg.matrix_rank(E) == ne
     Ed = np.zeros((ne, nd))
     Ed[:, :ne] = -np.eye(ne)
     Gd = np.zeros((nx, nd))
@@ -95,7 +123,7 @@ def barcelona_shaped_system(seed: int = 1) -> dict:
     tanks = np.concatenate([rng.permutation(nx), rng.integers(0, nx, size=len(tank_cols) - nx)])
     Gd[tanks, tank_cols] = -1.0
     xmax = 20.0 + rng.uniform(0.0, 30.0, nx)
-    umax = rng.uniform(2.0, 10.0, nu)
+    umax = np.where(is_src, rng.uniform(4.0, 12.0, nu), rng.uniform(2.0, 10.0, nu))
     pump_cols = np.sort(rng.choice(nu, size=N_PUMPS, replace=False))
     pump_weight = rng.uniform(0.0, 1.0, N_PUMPS)
     return {
@@ -106,7 +134,7 @@ def barcelona_shaped_system(seed: int = 1) -> dict:
         "W_alpha": 1.0, "alpha1": rng.uniform(0.5, 2.0, nu),
         "Wu": 5.0 * np.eye(nu), "W_x": 500.0, "gamma_d": 2500.0,
         "weight_safety_by_prob": 1,
-        "pump_cols": pump_cols, "pump_weight": pump_weight,
+        "pump_cols": pump_cols, "pump_weight": pump_weight, "source_cols": np.flatnonzero(is_src),
     }
 
 

@@ -1,0 +1,219 @@
+/*
+ * smpc.h -- C ABI of the MI355X (gfx950) solver for scenario-tree stochastic
+ * MPC by the accelerated dual proximal gradient method of Sampathirao,
+ * Sopasakis, Bemporad and Patrinos, "GPU-accelerated stochastic predictive
+ * control of drinking water networks" (arXiv 1604.01074).
+ *
+ * Problem solved (eq. Sc-MPC with the splitting of Sec. IV-A):
+ *
+ *   min  sum_n pi_n [ W_alpha (alpha1 + alpha2_{s(n)})' u_n
+ *                     + (u_n - u_{a(n)})' Wu (u_n - u_{a(n)}) ]
+ *      + sum_n [ cS_n dist(x_n | x >= xs) + gamma_d dist(x_n | [xmin, xmax]) ]
+ *   s.t. x_n = A x_{a(n)} + B u_n + Gd d_n,  E u_n + Ed d_n = 0,
+ *        umin <= u_n <= umax,  x_{a(root)} = p,  u_{a(root)} = q,
+ *
+ * over the decision nodes n of a scenario tree (Sec. III-C): node n sits at
+ * stage s(n) in 0..N-1, has parent a(n) and probability pi_n, and carries the
+ * demand d_n, the input u_n and the state x_n that follows it.  cS_n is
+ * W_x * pi_n (or W_x, see weight_safety_by_prob).
+ *
+ * Conventions for every call:
+ *  - Return value: 0 = SMPC_OK, > 0 = warning (outputs valid), < 0 = error.
+ *    No C++ exception crosses the ABI.  smpc_last_error() gives the message
+ *    of the last failing call on the calling thread.
+ *  - Matrices are dense, row-major, float64, host memory.  Inputs are copied
+ *    during the call; the caller keeps ownership of everything it passes.
+ *  - Outputs go to caller-allocated host buffers of the documented size.
+ *  - Node arrays use the caller's node order: stage-sorted, parent[n] < n.
+ *  - A dual vector has one block (sigma~_n [nx] | zeta~_n [nx] | psi~_n [nu])
+ *    per node (Sec. IV-A, dual of Hz = t), i.e. M x (2 nx + nu) row-major.
+ *  - All device work of a context runs on its one HIP stream, in order.
+ *    Handles are not thread-safe: use one context per host thread.
+ */
+#ifndef SMPC_H
+#define SMPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMPC_ABI_VERSION 1
+
+enum {
+  SMPC_OK = 0,
+  SMPC_MAX_ITER = 1,        /* warning: max_iter reached before tol; outputs valid */
+  SMPC_EINVAL = -1,         /* bad argument (NULL, negative size, bad flag)        */
+  SMPC_EDIM = -2,           /* dimension outside the supported range               */
+  SMPC_ENOTSPD = -3,        /* Wu not symmetric positive definite                  */
+  SMPC_ERANK = -4,          /* E does not have full row rank                       */
+  SMPC_EPROB = -5,          /* tree structure or probabilities inconsistent        */
+  SMPC_ENOMEM = -6,         /* device allocation failed or HBM budget exceeded     */
+  SMPC_EDEVICE = -7,        /* HIP runtime error                                   */
+  SMPC_ENOTFACTORED = -8,   /* smpc_factor / smpc_tree_set_data not called yet     */
+  SMPC_EDIVERGED = -9,      /* residual became non-finite or exploded              */
+  SMPC_ENAN = -10           /* NaN or Inf in an input                              */
+};
+
+typedef struct smpc_ctx smpc_ctx;
+typedef struct smpc_sys smpc_sys;
+typedef struct smpc_tree smpc_tree;
+
+/* ------------------------------------------------------------------ context
+ * smpc_ctx_create: bind to HIP device `device` and to the stream `hip_stream`
+ * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream); NULL makes
+ * the library create and own a stream.  `hbm_budget` caps the device bytes
+ * the context may allocate (0 = no cap); exceeding it gives SMPC_ENOMEM.
+ * Errors: SMPC_EINVAL (out == NULL), SMPC_EDEVICE (no such device).        */
+int smpc_ctx_create(int device, void* hip_stream, size_t hbm_budget, smpc_ctx** out);
+/* Frees the context.  All systems and trees of the context must be destroyed
+ * first (SMPC_EINVAL otherwise).                                             */
+int smpc_ctx_destroy(smpc_ctx* ctx);
+/* Copies the calling thread's last error message (NUL-terminated, truncated
+ * to len) into buf.  Returns the message length.                            */
+int smpc_last_error(char* buf, size_t len);
+/* Device bytes currently allocated by the context.                          */
+int smpc_ctx_mem_used(smpc_ctx* ctx, size_t* bytes);
+
+/* ------------------------------------------------------------------ system
+ * Flow model of Sec. II (eq. model, eq. demand-control), boxes and costs of
+ * Sec. III-A / III-D.  Sizes: A nx*nx, B nx*nu, Gd nx*nd, E ne*nu, Ed ne*nd
+ * (E, Ed may be NULL when ne == 0), umin/umax/alpha1 nu, xmin/xmax/xs nx,
+ * Wu nu*nu symmetric positive definite.
+ * weight_safety_by_prob: 1 -> safety weight of node n is W_x * pi_n (the
+ * expectation of the stage cost), 0 -> W_x.                                 */
+typedef struct {
+  int nx, nu, nd, ne;
+  const double *A, *B, *Gd, *E, *Ed;
+  const double *umin, *umax, *xmin, *xmax, *xs;
+  double W_alpha, W_x, gamma_d;
+  const double *alpha1, *Wu;
+  int weight_safety_by_prob;
+} smpc_sys_desc;
+
+/* Copies the system, checks it (SMPC_ENAN, SMPC_EDIM, SMPC_EINVAL for
+ * umin > umax or xmin > xmax, SMPC_ENOTSPD for Wu, SMPC_ERANK for E) and runs
+ * the tree-independent part of the factor step (App. A / App. B) in float64
+ * on the host.  Supported: 1 <= nx, 1 <= nu <= 136, 0 <= ne < nu,
+ * 2*nx + nu <= 1024.                                                         */
+int smpc_sys_create(smpc_ctx* ctx, const smpc_sys_desc* desc, smpc_sys** out);
+int smpc_sys_destroy(smpc_sys* sys);   /* SMPC_EINVAL while trees still use it */
+
+/* ------------------------------------------------------------------ tree
+ * Scenario tree (Sec. III-C) with N stages and M decision nodes, stage-sorted:
+ * stage[0] = 0, parent[0] = -1, parent[n] < n, stage[parent[n]] = stage[n]-1,
+ * every node at stage < N-1 has a child, prob > 0, prob[0] = 1 and the
+ * children of each node sum to its probability (relative 1e-9).
+ * Violations give SMPC_EPROB.  Allocates the tree's device buffers.          */
+int smpc_tree_create(smpc_sys* sys, int N, int M, const int32_t* stage,
+                     const int32_t* parent, const double* prob, smpc_tree** out);
+int smpc_tree_destroy(smpc_tree* tree);
+
+/* Cost update of App. A for new node demands d (M*nd, caller's node order)
+ * and pumping costs alpha2 (N*nu; NULL = zero).  Computes uhat_n, e_n and the
+ * linear cost terms in float64 on the host and uploads them.                 */
+int smpc_tree_set_data(smpc_tree* tree, const double* d, const double* alpha2);
+
+/* Step size and dual scaling (Sec. IV-D).
+ * precond: 0 -> no scaling; 1 -> one scalar per (node, dual block), the
+ *   inverse square root of the dual Hessian's diagonal averaged over the
+ *   block, taken from a single branch of the tree and divided by pi_n.
+ * scale: optional M*3 caller-given scaling (overrides precond when non-NULL).
+ * power_iters: power-iteration steps on the device for the largest
+ *   eigenvalue L of the (scaled) dual Hessian (default 200 when <= 0).
+ * lambda_override > 0 skips the power iteration and uses that step size.
+ * The step used is lambda = 1 / (L * (1 + margin)), margin = 0.02 when L
+ * comes from the power iteration.                                            */
+typedef struct {
+  int precond;
+  int power_iters;
+  double lambda_override;
+  const double* scale;
+} smpc_factor_opts;
+int smpc_factor(smpc_tree* tree, const smpc_factor_opts* opts);
+/* Step size lambda and, when scale != NULL, the M*3 dual scaling in use.    */
+int smpc_tree_get_factor(smpc_tree* tree, double* lambda, double* scale);
+/* Number of decision nodes, horizon, number of chains (maximal single-child
+ * paths) and chain levels of the tree.                                      */
+int smpc_tree_info(smpc_tree* tree, int* M, int* N, int* n_chains, int* n_levels);
+
+/* ------------------------------------------------------------------ solve
+ * APG iteration (eq. apg-iteration) from y^0 = y^{-1} and theta_0 = theta_{-1}
+ * = 1.  Every check_every iterations (and at the last one) the primal
+ * residual r_p = ||Hz - t||_inf is reduced in float64 and the solve stops when
+ * r_p <= tol * (1 + max(||Hz||_inf, ||t||_inf)); tol = 0 runs max_iter.
+ * precision 64: every step in float64.  precision 32: the solve step, prox and
+ * extrapolation run in float32 until the stop test passes (or max_iter -
+ * polish_iters is reached), then polish_iters more iterations run in float64
+ * from the float32 dual iterates.  Reductions are float64 in both modes.
+ * warm_start: 0 -> y0 = 0; 2 -> y^0 = y0 and y^{-1} = y_prev0 (or y0 when
+ * y_prev0 is NULL), both M*(2nx+nu) in the caller's node order.            */
+typedef struct {
+  double tol;
+  int max_iter;
+  int check_every;
+  int precision;
+  int polish_iters;
+  int warm_start;
+  const double* y0;
+  const double* y_prev0;
+} smpc_solve_opts;
+
+/* Caller-allocated outputs; any pointer may be NULL.  u0: nu, x: M*nx,
+ * u: M*nu (last primal iterate z^nu), y: M*(2nx+nu) (y^{nu+1}).
+ * iterations counts all iterations, fp32_iterations the float32 ones.
+ * status: SMPC_OK (stop test passed), SMPC_MAX_ITER or SMPC_EDIVERGED.      */
+typedef struct {
+  double* u0;
+  double* x;
+  double* u;
+  double* y;
+  int iterations;
+  int fp32_iterations;
+  double r_primal;
+  double hz_t_max;
+  int status;
+} smpc_result;
+
+/* Solve one tree from initial state p (nx) and previous input q (nu).
+ * Returns the result status (or an error).                                  */
+int smpc_solve(smpc_tree* tree, const double* p, const double* q,
+               const smpc_solve_opts* opts, smpc_result* res);
+
+/* Solve n distinct trees of one system together: every kernel launch covers
+ * the chains of all trees; a tree that has met its stop test stops iterating
+ * while the others go on.  Each tree's result equals its smpc_solve result
+ * bit for bit.  p[i], q[i] as in smpc_solve; res has n entries.  With
+ * warm_start 2, y0 (and y_prev0) hold the trees' dual vectors one after the
+ * other in batch order.  Returns the worst status over the trees.            */
+int smpc_solve_batch(smpc_tree* const* trees, int n, const double* const* p,
+                     const double* const* q, const smpc_solve_opts* opts,
+                     smpc_result* res);
+
+/* Solve step alone (Alg. 1): the primal point z(w) = argmin <z, H'w> + f(z)
+ * for a dual point w (M*(2nx+nu), caller's order), i.e. the dual gradient of
+ * Sec. IV-B.  precision 64 or 32.  Outputs x (M*nx) and u (M*nu).           */
+int smpc_solve_step(smpc_tree* tree, const double* p, const double* q,
+                    const double* w, int precision, double* x, double* u);
+
+/* ------------------------------------------------------------------ profiling
+ * With profiling on, every kernel launch is bracketed by HIP events on the
+ * context stream.  smpc_ctx_kernel_stats synchronises the stream and returns
+ * per-kernel totals since the last reset (up to cap entries, *n set to the
+ * number of distinct kernels).                                               */
+typedef struct {
+  char name[48];
+  int launches;
+  double total_ms;
+} smpc_kernel_stat;
+int smpc_ctx_set_profiling(smpc_ctx* ctx, int enable);
+int smpc_ctx_kernel_stats(smpc_ctx* ctx, smpc_kernel_stat* out, int cap, int* n);
+int smpc_ctx_reset_stats(smpc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMPC_H */

@@ -1,0 +1,1268 @@
+// C ABI of the scenario-tree SMPC solver: handles, validation, device buffers,
+// chain decomposition of the tree, launch plans and the iteration driver.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "smpc_host.h"
+
+using namespace smpc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+}  // namespace
+
+namespace smpc {
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+}  // namespace smpc
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return set_error(SMPC_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                       __FILE__, __LINE__);                                                \
+  } while (0)
+
+#define SMPC_TRY(expr)        \
+  do {                        \
+    int r_ = (expr);          \
+    if (r_ < 0) return r_;    \
+  } while (0)
+
+// ------------------------------------------------------------------ context
+
+int smpc_ctx::alloc(DevBuf& b, size_t bytes) {
+  if (b.ptr && b.bytes == bytes) return SMPC_OK;
+  release(b);
+  if (bytes == 0) return SMPC_OK;
+  if (budget && used + bytes > budget)
+    return set_error(SMPC_ENOMEM, "HBM budget exceeded: %zu + %zu > %zu bytes", used, bytes, budget);
+  hipError_t e = hipMalloc(&b.ptr, bytes);
+  if (e != hipSuccess) {
+    b.ptr = nullptr;
+    return set_error(SMPC_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  used += bytes;
+  return SMPC_OK;
+}
+
+void smpc_ctx::release(DevBuf& b) {
+  if (b.ptr) {
+    (void)hipFree(b.ptr);
+    used -= b.bytes;
+  }
+  b.ptr = nullptr;
+  b.bytes = 0;
+}
+
+int smpc_ctx::ensure_ctab(int n) {
+  if (n <= ctab_len) return SMPC_OK;
+  int len = std::max(n, 2 * ctab_len);
+  len = std::max(len, 1024);
+  std::vector<double> h(len);
+  // theta_0 = theta_{-1} = 1, theta_{k+1} = (sqrt(theta^4 + 4 theta^2) - theta^2) / 2
+  double th_prev = 1.0, th = 1.0;
+  for (int k = 0; k < len; ++k) {
+    h[k] = th * (1.0 / th_prev - 1.0);
+    const double nt = 0.5 * (std::sqrt(th * th * th * th + 4.0 * th * th) - th * th);
+    th_prev = th;
+    th = nt;
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (ctab) {
+    (void)hipFree(ctab);
+    used -= sizeof(double) * (size_t)ctab_len;
+  }
+  ctab = nullptr;
+  ctab_len = 0;
+  if (budget && used + sizeof(double) * len > budget) return set_error(SMPC_ENOMEM, "HBM budget exceeded");
+  HIP_TRY(hipMalloc(&ctab, sizeof(double) * len));
+  used += sizeof(double) * len;
+  HIP_TRY(hipMemcpy(ctab, h.data(), sizeof(double) * len, hipMemcpyHostToDevice));
+  ctab_len = len;
+  return SMPC_OK;
+}
+
+hipEvent_t smpc_ctx::get_event() {
+  if (!ev_pool.empty()) {
+    hipEvent_t e = ev_pool.back();
+    ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void smpc_ctx::flush_profile() {
+  if (prof.empty()) return;
+  (void)hipStreamSynchronize(stream);
+  for (auto& r : prof) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    auto& s = stats[r.name];
+    s.first += 1;
+    s.second += ms;
+    ev_pool.push_back(r.a);
+    ev_pool.push_back(r.b);
+  }
+  prof.clear();
+}
+
+namespace {
+
+// Bracket one launch with events when profiling is on.
+template <typename F>
+hipError_t timed(smpc_ctx* ctx, const char* name, F&& f) {
+  if (!ctx->profiling) return f();
+  hipEvent_t a = ctx->get_event(), b = ctx->get_event();
+  (void)hipEventRecord(a, ctx->stream);
+  hipError_t e = f();
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->prof.push_back({name, a, b});
+  if (ctx->prof.size() > 4096) ctx->flush_profile();
+  return e;
+}
+
+bool all_finite(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+template <typename T>
+int upload(smpc_ctx* ctx, DevBuf& b, const double* src, size_t n) {
+  SMPC_TRY(ctx->alloc(b, sizeof(T) * std::max<size_t>(n, 1)));
+  if (n == 0) return SMPC_OK;
+  std::vector<T> h(n);
+  for (size_t i = 0; i < n; ++i) h[i] = (T)src[i];
+  HIP_TRY(hipMemcpyAsync(b.ptr, h.data(), sizeof(T) * n, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return SMPC_OK;
+}
+
+int upload_i32(smpc_ctx* ctx, DevBuf& b, const std::vector<int32_t>& v) {
+  SMPC_TRY(ctx->alloc(b, sizeof(int32_t) * std::max<size_t>(v.size(), 1)));
+  if (v.empty()) return SMPC_OK;
+  HIP_TRY(hipMemcpyAsync(b.ptr, v.data(), sizeof(int32_t) * v.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return SMPC_OK;
+}
+
+template <typename T>
+int sys_upload(smpc_sys* s, SysBuffers<T>& d) {
+  smpc_ctx* ctx = s->ctx;
+  SMPC_TRY(upload<T>(ctx, d.P, s->P.data(), s->P.size()));
+  SMPC_TRY(upload_i32(ctx, d.b_rp, s->Bc.rp));
+  SMPC_TRY(upload_i32(ctx, d.b_ci, s->Bc.ci));
+  SMPC_TRY(upload<T>(ctx, d.b_v, s->Bc.v.data(), s->Bc.v.size()));
+  SMPC_TRY(upload_i32(ctx, d.bt_rp, s->Btc.rp));
+  SMPC_TRY(upload_i32(ctx, d.bt_ci, s->Btc.ci));
+  SMPC_TRY(upload<T>(ctx, d.bt_v, s->Btc.v.data(), s->Btc.v.size()));
+  SMPC_TRY(upload_i32(ctx, d.a_rp, s->Ac.rp));
+  SMPC_TRY(upload_i32(ctx, d.a_ci, s->Ac.ci));
+  SMPC_TRY(upload<T>(ctx, d.a_v, s->Ac.v.data(), s->Ac.v.size()));
+  SMPC_TRY(upload_i32(ctx, d.at_rp, s->Atc.rp));
+  SMPC_TRY(upload_i32(ctx, d.at_ci, s->Atc.ci));
+  SMPC_TRY(upload<T>(ctx, d.at_v, s->Atc.v.data(), s->Atc.v.size()));
+  SMPC_TRY(upload<T>(ctx, d.umin, s->umin.data(), s->nu));
+  SMPC_TRY(upload<T>(ctx, d.umax, s->umax.data(), s->nu));
+  SMPC_TRY(upload<T>(ctx, d.xmin, s->xmin.data(), s->nx));
+  SMPC_TRY(upload<T>(ctx, d.xmax, s->xmax.data(), s->nx));
+  SMPC_TRY(upload<T>(ctx, d.xs, s->xs.data(), s->nx));
+  SysDev<T>& v = d.view;
+  v.nx = s->nx;
+  v.nu = s->nu;
+  v.D = 2 * s->nx + s->nu;
+  v.a_identity = s->a_identity;
+  v.P = (const T*)d.P.ptr;
+  v.b_rp = (const int32_t*)d.b_rp.ptr;
+  v.b_ci = (const int32_t*)d.b_ci.ptr;
+  v.b_v = (const T*)d.b_v.ptr;
+  v.bt_rp = (const int32_t*)d.bt_rp.ptr;
+  v.bt_ci = (const int32_t*)d.bt_ci.ptr;
+  v.bt_v = (const T*)d.bt_v.ptr;
+  v.a_rp = (const int32_t*)d.a_rp.ptr;
+  v.a_ci = (const int32_t*)d.a_ci.ptr;
+  v.a_v = (const T*)d.a_v.ptr;
+  v.at_rp = (const int32_t*)d.at_rp.ptr;
+  v.at_ci = (const int32_t*)d.at_ci.ptr;
+  v.at_v = (const T*)d.at_v.ptr;
+  v.umin = (const T*)d.umin.ptr;
+  v.umax = (const T*)d.umax.ptr;
+  v.xmin = (const T*)d.xmin.ptr;
+  v.xmax = (const T*)d.xmax.ptr;
+  v.xs = (const T*)d.xs.ptr;
+  v.W_x = s->W_x;
+  v.gamma_d = s->gamma_d;
+  v.safety_by_prob = s->safety_by_prob;
+  return SMPC_OK;
+}
+
+template <typename T>
+void sys_free(smpc_ctx* ctx, SysBuffers<T>& d) {
+  DevBuf* all[] = {&d.P, &d.b_rp, &d.b_ci, &d.b_v, &d.bt_rp, &d.bt_ci, &d.bt_v, &d.a_rp, &d.a_ci,
+                   &d.a_v, &d.at_rp, &d.at_ci, &d.at_v, &d.umin, &d.umax, &d.xmin, &d.xmax, &d.xs};
+  for (DevBuf* b : all) ctx->release(*b);
+}
+
+template <typename T>
+SysBuffers<T>& sysbuf(smpc_sys* s);
+template <>
+SysBuffers<double>& sysbuf<double>(smpc_sys* s) { return s->d64; }
+template <>
+SysBuffers<float>& sysbuf<float>(smpc_sys* s) { return s->d32; }
+
+template <typename T>
+TreeBuffers<T>& treebuf(smpc_tree* t);
+template <>
+TreeBuffers<double>& treebuf<double>(smpc_tree* t) { return t->b64; }
+template <>
+TreeBuffers<float>& treebuf<float>(smpc_tree* t) { return t->b32; }
+
+int ensure_sys32(smpc_sys* s) {
+  if (s->has32) return SMPC_OK;
+  SMPC_TRY(sys_upload<float>(s, s->d32));
+  s->has32 = true;
+  return SMPC_OK;
+}
+
+// Allocate the per-precision node buffers of a tree and upload what is known.
+template <typename T>
+int tree_alloc(smpc_tree* t) {
+  TreeBuffers<T>& b = treebuf<T>(t);
+  smpc_ctx* ctx = t->sys->ctx;
+  const size_t M = t->M, nx = t->sys->nx, nu = t->sys->nu, D = 2 * nx + nu, C = t->chains.size();
+  if (!b.allocated) {
+    for (int k = 0; k < 3; ++k) SMPC_TRY(ctx->alloc(b.y[k], sizeof(T) * M * D));
+    SMPC_TRY(ctx->alloc(b.beta, sizeof(T) * M * nu));
+    SMPC_TRY(ctx->alloc(b.uhat, sizeof(T) * M * nu));
+    SMPC_TRY(ctx->alloc(b.e, sizeof(T) * M * nx));
+    SMPC_TRY(ctx->alloc(b.pi, sizeof(T) * M));
+    SMPC_TRY(ctx->alloc(b.scale, sizeof(T) * M * 3));
+    SMPC_TRY(ctx->alloc(b.p, sizeof(T) * nx));
+    SMPC_TRY(ctx->alloc(b.du, sizeof(T) * M * nu));
+    SMPC_TRY(ctx->alloc(b.z, sizeof(T) * M * (nx + nu)));
+    SMPC_TRY(ctx->alloc(b.ctopQ, sizeof(T) * C * nx));
+    SMPC_TRY(ctx->alloc(b.ctopR, sizeof(T) * C * nu));
+    SMPC_TRY(ctx->alloc(b.cbotX, sizeof(T) * C * nx));
+    SMPC_TRY(ctx->alloc(b.cbotU, sizeof(T) * C * nu));
+    for (int k = 0; k < 3; ++k) HIP_TRY(hipMemsetAsync(b.y[k].ptr, 0, sizeof(T) * M * D, ctx->stream));
+    b.allocated = true;
+    std::vector<double> pii(M);
+    for (size_t i = 0; i < M; ++i) pii[i] = t->prob[t->perm[i]];
+    SMPC_TRY(upload<T>(ctx, b.pi, pii.data(), M));
+  }
+  TreeDev<T>& v = b.view;
+  for (int k = 0; k < 3; ++k) v.y[k] = (T*)b.y[k].ptr;
+  v.beta = (const T*)b.beta.ptr;
+  v.uhat = (const T*)b.uhat.ptr;
+  v.e = (const T*)b.e.ptr;
+  v.pi = (const T*)b.pi.ptr;
+  v.scale = t->scale.empty() ? nullptr : (const T*)b.scale.ptr;
+  v.p = (const T*)b.p.ptr;
+  v.du = (T*)b.du.ptr;
+  v.z = (T*)b.z.ptr;
+  v.ctopQ = (T*)b.ctopQ.ptr;
+  v.ctopR = (T*)b.ctopR.ptr;
+  v.cbotX = (T*)b.cbotX.ptr;
+  v.cbotU = (T*)b.cbotU.ptr;
+  v.cstat = (double*)t->cstat.ptr;
+  v.chains = (const ChainDesc*)t->chains_dev.ptr;
+  v.st = (TreeState*)t->st.ptr;
+  v.n_chains = (int32_t)C;
+  v.M = (int32_t)M;
+  return SMPC_OK;
+}
+
+template <typename T>
+void tree_free(smpc_ctx* ctx, TreeBuffers<T>& b) {
+  DevBuf* all[] = {&b.y[0], &b.y[1], &b.y[2], &b.beta, &b.uhat, &b.e, &b.pi, &b.scale, &b.p,
+                   &b.du, &b.z, &b.ctopQ, &b.ctopR, &b.cbotX, &b.cbotU};
+  for (DevBuf* d : all) ctx->release(*d);
+  b.allocated = false;
+}
+
+// Upload the cost-update vectors and the scaling of one precision.
+template <typename T>
+int tree_upload_data(smpc_tree* t) {
+  TreeBuffers<T>& b = treebuf<T>(t);
+  smpc_ctx* ctx = t->sys->ctx;
+  SMPC_TRY(upload<T>(ctx, b.beta, t->beta0.data(), t->beta0.size()));
+  SMPC_TRY(upload<T>(ctx, b.uhat, t->uhat.data(), t->uhat.size()));
+  SMPC_TRY(upload<T>(ctx, b.e, t->e.data(), t->e.size()));
+  return SMPC_OK;
+}
+
+template <typename T>
+int tree_upload_scale(smpc_tree* t) {
+  TreeBuffers<T>& b = treebuf<T>(t);
+  if (t->scale.empty()) return SMPC_OK;
+  return upload<T>(t->sys->ctx, b.scale, t->scale.data(), t->scale.size());
+}
+
+void plan_free(smpc_ctx* ctx, Plan* p) {
+  if (!p) return;
+  ctx->release(p->items);
+  ctx->release(p->td64);
+  ctx->release(p->td32);
+  ctx->release(p->refs);
+  ctx->release(p->done);
+  delete p;
+}
+
+// Build the launch plan of a set of trees: for every chain height, the work
+// items of all trees (longest chains first), and the device tree tables.
+int plan_build(smpc_ctx* ctx, const std::vector<smpc_tree*>& trees, bool need32, Plan** out) {
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return set_error(SMPC_ENOMEM, "host allocation failed");
+  p->trees = trees;
+  int H = 0;
+  for (auto* t : trees) H = std::max(H, t->n_levels);
+  p->H = H;
+  std::vector<WorkItem> items;
+  for (int h = 0; h < H; ++h) {
+    p->lvl_off.push_back((int)items.size());
+    std::vector<std::pair<int, WorkItem>> lvl;
+    for (size_t k = 0; k < trees.size(); ++k) {
+      const smpc_tree* t = trees[k];
+      if (h >= t->n_levels) continue;
+      for (int32_t c : t->level_chains[h]) lvl.push_back({t->chains[c].len, WorkItem{(int32_t)k, c}});
+    }
+    std::stable_sort(lvl.begin(), lvl.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    for (auto& w : lvl) items.push_back(w.second);
+    p->lvl_cnt.push_back((int)items.size() - p->lvl_off.back());
+  }
+  int rc = ctx->alloc(p->items, sizeof(WorkItem) * std::max<size_t>(items.size(), 1));
+  if (rc < 0) { plan_free(ctx, p); return rc; }
+  std::vector<TreeDev<double>> t64;
+  std::vector<TreeDev<float>> t32;
+  std::vector<IterRef> refs;
+  rc = ctx->alloc(p->done, sizeof(int32_t) * trees.size());
+  if (rc < 0) { plan_free(ctx, p); return rc; }
+  for (size_t k = 0; k < trees.size(); ++k) {
+    smpc_tree* t = trees[k];
+    t64.push_back(t->b64.view);
+    if (need32) t32.push_back(t->b32.view);
+    IterRef r{};
+    r.st = (TreeState*)t->st.ptr;
+    r.cstat = (const double*)t->cstat.ptr;
+    r.done_out = (int32_t*)p->done.ptr;
+    r.n_chains = (int32_t)t->chains.size();
+    r.slot = (int32_t)k;
+    refs.push_back(r);
+  }
+  rc = ctx->alloc(p->td64, sizeof(TreeDev<double>) * t64.size());
+  if (rc >= 0 && need32) rc = ctx->alloc(p->td32, sizeof(TreeDev<float>) * t32.size());
+  if (rc >= 0) rc = ctx->alloc(p->refs, sizeof(IterRef) * refs.size());
+  if (rc < 0) { plan_free(ctx, p); return rc; }
+  hipStream_t s = ctx->stream;
+  hipError_t e = hipSuccess;
+  if (!items.empty()) e = hipMemcpyAsync(p->items.ptr, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->td64.ptr, t64.data(), sizeof(TreeDev<double>) * t64.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && need32) e = hipMemcpyAsync(p->td32.ptr, t32.data(), sizeof(TreeDev<float>) * t32.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->refs.ptr, refs.data(), sizeof(IterRef) * refs.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    plan_free(ctx, p);
+    return set_error(SMPC_EDEVICE, "plan upload failed: %s", hipGetErrorString(e));
+  }
+  p->done_host.assign(trees.size(), 0);
+  p->has32 = need32;
+  *out = p;
+  return SMPC_OK;
+}
+
+template <typename T>
+const TreeDev<T>* plan_td(Plan* p);
+template <>
+const TreeDev<double>* plan_td<double>(Plan* p) { return (const TreeDev<double>*)p->td64.ptr; }
+template <>
+const TreeDev<float>* plan_td<float>(Plan* p) { return (const TreeDev<float>*)p->td32.ptr; }
+
+template <typename T>
+const char* kname(int which, int h);
+template <>
+const char* kname<double>(int which, int h) {
+  static const char* n[3][2] = {{"backward_leaf_f64", "backward_inner_f64"},
+                                {"forward_leaf_f64", "forward_inner_f64"},
+                                {"iter_end", "iter_end"}};
+  return n[which][h == 0 ? 0 : 1];
+}
+template <>
+const char* kname<float>(int which, int h) {
+  static const char* n[3][2] = {{"backward_leaf_f32", "backward_inner_f32"},
+                                {"forward_leaf_f32", "forward_inner_f32"},
+                                {"iter_end", "iter_end"}};
+  return n[which][h == 0 ? 0 : 1];
+}
+
+// Enqueue one iteration (all levels backward, all levels forward, then the
+// per-tree bookkeeping) of `mode` for every tree of the plan.
+template <typename T>
+int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, bool with_end) {
+  const SysDev<T>& sv = sysbuf<T>(sys).view;
+  const TreeDev<T>* td = plan_td<T>(p);
+  const WorkItem* items = (const WorkItem*)p->items.ptr;
+  hipStream_t s = ctx->stream;
+  for (int h = 0; h < p->H; ++h) {
+    HIP_TRY(timed(ctx, kname<T>(0, h), [&] {
+      return launch_backward<T>(sv, td, items + p->lvl_off[h], p->lvl_cnt[h], ctx->ctab, mode, s);
+    }));
+  }
+  for (int h = p->H - 1; h >= 0; --h) {
+    HIP_TRY(timed(ctx, kname<T>(1, h), [&] {
+      return launch_forward<T>(sv, td, items + p->lvl_off[h], p->lvl_cnt[h], ctx->ctab, mode, s);
+    }));
+  }
+  if (with_end) {
+    HIP_TRY(timed(ctx, "iter_end", [&] { return launch_iter_end_refs(p->refs.ptr, (int)p->trees.size(), mode, s); }));
+  }
+  return SMPC_OK;
+}
+
+// Run APG iterations until every tree of the plan is done.
+template <typename T>
+int run_until_done(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int check_every, int max_rounds) {
+  for (int round = 0; round < max_rounds; ++round) {
+    for (int k = 0; k < check_every; ++k) SMPC_TRY(enqueue_iteration<T>(ctx, sys, p, kModeAPG, true));
+    HIP_TRY(hipMemcpyAsync(p->done_host.data(), p->done.ptr, sizeof(int32_t) * p->trees.size(),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    bool all = true;
+    for (int32_t d : p->done_host) all = all && d;
+    if (all) return SMPC_OK;
+  }
+  return set_error(SMPC_EDEVICE, "iteration driver did not terminate");
+}
+
+int read_state(smpc_tree* t, TreeState* h) {
+  HIP_TRY(hipMemcpyAsync(h, t->st.ptr, sizeof(TreeState), hipMemcpyDeviceToHost, t->sys->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(t->sys->ctx->stream));
+  return SMPC_OK;
+}
+
+int write_state(smpc_tree* t, const TreeState& h) {
+  HIP_TRY(hipMemcpyAsync(t->st.ptr, &h, sizeof(TreeState), hipMemcpyHostToDevice, t->sys->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(t->sys->ctx->stream));
+  return SMPC_OK;
+}
+
+// Per-solve inputs: root parent state p and the root's linear term (depends on q).
+template <typename T>
+int upload_root(smpc_tree* t, const double* p, const double* q) {
+  TreeBuffers<T>& b = treebuf<T>(t);
+  smpc_ctx* ctx = t->sys->ctx;
+  const int nx = t->sys->nx, nu = t->sys->nu;
+  std::vector<T> hp(nx);
+  for (int i = 0; i < nx; ++i) hp[i] = (T)p[i];
+  std::vector<double> br;
+  root_beta(t, q, br);
+  std::vector<T> hb(nu);
+  for (int i = 0; i < nu; ++i) hb[i] = (T)br[i];
+  const size_t r = (size_t)t->iperm[0];
+  HIP_TRY(hipMemcpyAsync(b.p.ptr, hp.data(), sizeof(T) * nx, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipMemcpyAsync((T*)b.beta.ptr + r * nu, hb.data(), sizeof(T) * nu, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return SMPC_OK;
+}
+
+// Initial dual iterates (scaled, internal order): y^0 -> y[0], y^{-1} -> y[2].
+template <typename T>
+int upload_dual_start(smpc_tree* t, const double* y0, const double* yprev0) {
+  TreeBuffers<T>& b = treebuf<T>(t);
+  smpc_ctx* ctx = t->sys->ctx;
+  const int nx = t->sys->nx, nu = t->sys->nu, D = 2 * nx + nu, M = t->M;
+  if (!y0) {
+    HIP_TRY(hipMemsetAsync(b.y[0].ptr, 0, sizeof(T) * M * D, ctx->stream));
+    HIP_TRY(hipMemsetAsync(b.y[2].ptr, 0, sizeof(T) * M * D, ctx->stream));
+    return SMPC_OK;
+  }
+  std::vector<T> h((size_t)M * D);
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* src = pass == 0 ? y0 : (yprev0 ? yprev0 : y0);
+    for (int in = 0; in < M; ++in) {
+      const int n = t->perm[in];
+      for (int k = 0; k < D; ++k) {
+        const int blk = k < nx ? 0 : (k < 2 * nx ? 1 : 2);
+        const double s = t->scale.empty() ? 1.0 : t->scale[(size_t)in * 3 + blk];
+        h[(size_t)in * D + k] = (T)(src[(size_t)n * D + k] / s);
+      }
+    }
+    HIP_TRY(hipMemcpyAsync(b.y[pass == 0 ? 0 : 2].ptr, h.data(), sizeof(T) * M * D, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  return SMPC_OK;
+}
+
+template <typename T>
+int download_primal(smpc_tree* t, double* x, double* u, double* u0) {
+  TreeBuffers<T>& b = treebuf<T>(t);
+  smpc_ctx* ctx = t->sys->ctx;
+  const int nx = t->sys->nx, nu = t->sys->nu, M = t->M, nz = nx + nu;
+  std::vector<T> h;
+  if (x || u) {
+    h.resize((size_t)M * nz);
+    HIP_TRY(hipMemcpyAsync(h.data(), b.z.ptr, sizeof(T) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (int in = 0; in < M; ++in) {
+      const int n = t->perm[in];
+      if (x)
+        for (int i = 0; i < nx; ++i) x[(size_t)n * nx + i] = (double)h[(size_t)in * nz + i];
+      if (u)
+        for (int j = 0; j < nu; ++j) u[(size_t)n * nu + j] = (double)h[(size_t)in * nz + nx + j];
+    }
+    if (u0) {
+      const int r = t->iperm[0];
+      for (int j = 0; j < nu; ++j) u0[j] = (double)h[(size_t)r * nz + nx + j];
+    }
+  } else if (u0) {
+    std::vector<T> hr(nu);
+    const size_t r = (size_t)t->iperm[0];
+    HIP_TRY(hipMemcpyAsync(hr.data(), (T*)b.z.ptr + r * nz + nx, sizeof(T) * nu, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (int j = 0; j < nu; ++j) u0[j] = (double)hr[j];
+  }
+  return SMPC_OK;
+}
+
+template <typename T>
+int download_dual(smpc_tree* t, int slot, double* y) {
+  TreeBuffers<T>& b = treebuf<T>(t);
+  smpc_ctx* ctx = t->sys->ctx;
+  const int nx = t->sys->nx, nu = t->sys->nu, D = 2 * nx + nu, M = t->M;
+  std::vector<T> h((size_t)M * D);
+  HIP_TRY(hipMemcpyAsync(h.data(), b.y[slot].ptr, sizeof(T) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int in = 0; in < M; ++in) {
+    const int n = t->perm[in];
+    for (int k = 0; k < D; ++k) {
+      const int blk = k < nx ? 0 : (k < 2 * nx ? 1 : 2);
+      const double s = t->scale.empty() ? 1.0 : t->scale[(size_t)in * 3 + blk];
+      y[(size_t)n * D + k] = s * (double)h[(size_t)in * D + k];
+    }
+  }
+  return SMPC_OK;
+}
+
+int check_opts(const smpc_solve_opts* o) {
+  if (!o) return set_error(SMPC_EINVAL, "opts is NULL");
+  if (o->max_iter < 1) return set_error(SMPC_EINVAL, "max_iter must be >= 1");
+  if (o->check_every < 1) return set_error(SMPC_EINVAL, "check_every must be >= 1");
+  if (o->precision != 64 && o->precision != 32) return set_error(SMPC_EINVAL, "precision must be 32 or 64");
+  if (o->polish_iters < 0 || o->polish_iters > o->max_iter) return set_error(SMPC_EINVAL, "polish_iters out of range");
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return set_error(SMPC_EINVAL, "tol must be finite and >= 0");
+  if (o->warm_start != 0 && o->warm_start != 2) return set_error(SMPC_EINVAL, "warm_start must be 0 or 2");
+  if (o->warm_start == 2 && !o->y0) return set_error(SMPC_EINVAL, "warm_start 2 needs y0");
+  return SMPC_OK;
+}
+
+// Solve a set of trees (one plan) with the given options.
+int solve_plan(Plan* plan, const double* const* p, const double* const* q, const smpc_solve_opts* o,
+               smpc_result* res) {
+  smpc_sys* sys = plan->trees[0]->sys;
+  smpc_ctx* ctx = sys->ctx;
+  const int n = (int)plan->trees.size();
+  const int D = 2 * sys->nx + sys->nu;
+  SMPC_TRY(ctx->ensure_ctab(o->max_iter + 2));
+  const bool use32 = o->precision == 32;
+  const int polish = use32 ? o->polish_iters : 0;
+  const int max32 = o->max_iter - polish;
+  const int max_rounds = o->max_iter / o->check_every + 3;
+  std::vector<int> fp32_iters(n, 0), status32(n, 0);
+  const bool run32 = use32 && max32 > 0;
+
+  for (int k = 0; k < n; ++k) {
+    smpc_tree* t = plan->trees[k];
+    SMPC_TRY(upload_root<double>(t, p[k], q[k]));
+    if (run32) {
+      SMPC_TRY(upload_root<float>(t, p[k], q[k]));
+    }
+  }
+  // dual starting points
+  {
+    size_t off = 0;
+    for (int k = 0; k < n; ++k) {
+      smpc_tree* t = plan->trees[k];
+      const double* y0 = o->warm_start == 2 ? o->y0 + off : nullptr;
+      const double* yp0 = (o->warm_start == 2 && o->y_prev0) ? o->y_prev0 + off : nullptr;
+      if (run32) SMPC_TRY(upload_dual_start<float>(t, y0, yp0));
+      else SMPC_TRY(upload_dual_start<double>(t, y0, yp0));
+      off += (size_t)t->M * D;
+    }
+  }
+  auto init_state = [&](smpc_tree* t, int iter, int max_iter, double tol) {
+    TreeState h{};
+    h.iter = iter;
+    h.done = 0;
+    h.max_iter = max_iter;
+    h.check_every = o->check_every;
+    h.status = 0;
+    h.iters_done = 0;
+    h.tol = tol;
+    h.lambda = t->lambda;
+    h.in_scale = 1.0;
+    return write_state(t, h);
+  };
+  if (run32) {
+    for (int k = 0; k < n; ++k) SMPC_TRY(init_state(plan->trees[k], 0, max32, o->tol));
+    SMPC_TRY(run_until_done<float>(ctx, sys, plan, o->check_every, max_rounds));
+    for (int k = 0; k < n; ++k) {
+      TreeState h;
+      SMPC_TRY(read_state(plan->trees[k], &h));
+      fp32_iters[k] = h.iters_done;
+      status32[k] = h.status;
+    }
+  }
+  const bool run64 = !use32 || polish > 0;
+  if (run64) {
+    for (int k = 0; k < n; ++k) {
+      smpc_tree* t = plan->trees[k];
+      if (run32) {
+        // continue in float64 from the float32 iterates (all three slots)
+        TreeBuffers<float>& b32 = t->b32;
+        TreeBuffers<double>& b64 = t->b64;
+        for (int s = 0; s < 3; ++s)
+          HIP_TRY(launch_widen<float>((const float*)b32.y[s].ptr, (double*)b64.y[s].ptr, (size_t)t->M * D, ctx->stream));
+        if (status32[k] == -9) {
+          SMPC_TRY(init_state(t, fp32_iters[k], fp32_iters[k], 0.0));
+          TreeState h;
+          SMPC_TRY(read_state(t, &h));
+          h.done = 1;
+          h.status = -9;
+          h.iters_done = fp32_iters[k];
+          SMPC_TRY(write_state(t, h));
+        } else {
+          SMPC_TRY(init_state(t, fp32_iters[k], fp32_iters[k] + polish, 0.0));
+        }
+      } else {
+        SMPC_TRY(init_state(t, 0, o->max_iter, o->tol));
+      }
+    }
+    SMPC_TRY(run_until_done<double>(ctx, sys, plan, use32 ? std::max(1, std::min(o->check_every, polish)) : o->check_every,
+                                    max_rounds + polish + 2));
+  }
+  for (int k = 0; k < n; ++k) {
+    smpc_tree* t = plan->trees[k];
+    TreeState h;
+    SMPC_TRY(read_state(t, &h));
+    smpc_result* r = res ? &res[k] : nullptr;
+    if (!r) continue;
+    r->iterations = h.iters_done;
+    r->fp32_iterations = run32 ? fp32_iters[k] : 0;
+    r->r_primal = h.r_p;
+    r->hz_t_max = h.hzt;
+    int status;
+    if (h.status == -9 || (run32 && status32[k] == -9)) status = SMPC_EDIVERGED;
+    else if (run32) status = status32[k] == 0 ? SMPC_OK : SMPC_MAX_ITER;
+    else status = h.status == 0 ? SMPC_OK : SMPC_MAX_ITER;
+    r->status = status;
+    if (run64) {
+      SMPC_TRY(download_primal<double>(t, r->x, r->u, r->u0));
+      if (r->y) SMPC_TRY(download_dual<double>(t, h.iters_done % 3, r->y));
+    } else {
+      SMPC_TRY(download_primal<float>(t, r->x, r->u, r->u0));
+      if (r->y) SMPC_TRY(download_dual<float>(t, h.iters_done % 3, r->y));
+    }
+  }
+  return SMPC_OK;
+}
+
+uint64_t splitmix(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ULL;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+  return x ^ (x >> 31);
+}
+
+int tree_check_ready(smpc_tree* t, bool need_data) {
+  if (!t) return set_error(SMPC_EINVAL, "tree is NULL");
+  if (need_data && !t->has_data) return set_error(SMPC_ENOTFACTORED, "smpc_tree_set_data not called");
+  if (need_data && !t->factored) return set_error(SMPC_ENOTFACTORED, "smpc_factor not called");
+  return SMPC_OK;
+}
+
+int ensure_single_plan(smpc_tree* t, bool need32) {
+  smpc_ctx* ctx = t->sys->ctx;
+  if (t->plan && (!need32 || t->plan->has32)) return SMPC_OK;
+  if (t->plan) {
+    plan_free(ctx, t->plan);
+    t->plan = nullptr;
+  }
+  return plan_build(ctx, {t}, need32, &t->plan);
+}
+
+int prepare32(smpc_tree* t) {
+  SMPC_TRY(ensure_sys32(t->sys));
+  if (!t->b32.allocated) {
+    SMPC_TRY(tree_alloc<float>(t));
+    if (t->has_data) SMPC_TRY(tree_upload_data<float>(t));
+    SMPC_TRY(tree_upload_scale<float>(t));
+    SMPC_TRY(tree_alloc<float>(t));
+    if (t->plan) {
+      plan_free(t->sys->ctx, t->plan);
+      t->plan = nullptr;
+    }
+  }
+  return SMPC_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+int smpc_last_error(char* buf, size_t len) {
+  if (buf && len) {
+    std::strncpy(buf, g_last_error.c_str(), len - 1);
+    buf[len - 1] = '\0';
+  }
+  return (int)g_last_error.size();
+}
+
+int smpc_ctx_create(int device, void* hip_stream, size_t hbm_budget, smpc_ctx** out) {
+  if (!out) return set_error(SMPC_EINVAL, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return set_error(SMPC_EDEVICE, "no HIP device %d (%d visible)", device, count);
+  HIP_TRY(hipSetDevice(device));
+  smpc_ctx* c = new (std::nothrow) smpc_ctx();
+  if (!c) return set_error(SMPC_ENOMEM, "host allocation failed");
+  c->device = device;
+  c->budget = hbm_budget;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return set_error(SMPC_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return SMPC_OK;
+}
+
+int smpc_ctx_destroy(smpc_ctx* ctx) {
+  if (!ctx) return SMPC_OK;
+  if (ctx->n_sys > 0) return set_error(SMPC_EINVAL, "context still has %d systems", ctx->n_sys);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->flush_profile();
+  if (ctx->batch_plan) plan_free(ctx, ctx->batch_plan);
+  if (ctx->ctab) (void)hipFree(ctx->ctab);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return SMPC_OK;
+}
+
+int smpc_ctx_mem_used(smpc_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return set_error(SMPC_EINVAL, "NULL argument");
+  *bytes = ctx->used;
+  return SMPC_OK;
+}
+
+int smpc_sys_create(smpc_ctx* ctx, const smpc_sys_desc* d, smpc_sys** out) {
+  if (!ctx || !d || !out) return set_error(SMPC_EINVAL, "NULL argument");
+  *out = nullptr;
+  const int nx = d->nx, nu = d->nu, nd = d->nd, ne = d->ne;
+  if (nx < 1 || nu < 1 || nd < 0 || ne < 0) return set_error(SMPC_EDIM, "dimensions must be positive");
+  if (nu > 136) return set_error(SMPC_EDIM, "nu = %d exceeds the supported 136", nu);
+  if (ne >= nu) return set_error(SMPC_EDIM, "ne = %d must be < nu = %d", ne, nu);
+  if (2 * nx + nu > 4 * kBlock) return set_error(SMPC_EDIM, "2 nx + nu = %d exceeds %d", 2 * nx + nu, 4 * kBlock);
+  if (!d->A || !d->B || (nd > 0 && !d->Gd) || !d->umin || !d->umax || !d->xmin || !d->xmax || !d->xs ||
+      !d->alpha1 || !d->Wu)
+    return set_error(SMPC_EINVAL, "missing system matrix");
+  if (ne > 0 && (!d->E || (nd > 0 && !d->Ed))) return set_error(SMPC_EINVAL, "missing E / Ed");
+  smpc_sys* s = new (std::nothrow) smpc_sys();
+  if (!s) return set_error(SMPC_ENOMEM, "host allocation failed");
+  s->ctx = ctx;
+  s->nx = nx; s->nu = nu; s->nd = nd; s->ne = ne;
+  auto cp = [](std::vector<double>& v, const double* p, size_t n) { v.assign(p ? p : nullptr, p ? p + n : nullptr); if (!p) v.assign(n, 0.0); };
+  cp(s->A, d->A, (size_t)nx * nx);
+  cp(s->B, d->B, (size_t)nx * nu);
+  cp(s->Gd, d->Gd, (size_t)nx * nd);
+  cp(s->E, ne ? d->E : nullptr, (size_t)ne * nu);
+  cp(s->Ed, ne ? d->Ed : nullptr, (size_t)ne * nd);
+  cp(s->umin, d->umin, nu);
+  cp(s->umax, d->umax, nu);
+  cp(s->xmin, d->xmin, nx);
+  cp(s->xmax, d->xmax, nx);
+  cp(s->xs, d->xs, nx);
+  cp(s->alpha1, d->alpha1, nu);
+  cp(s->Wu, d->Wu, (size_t)nu * nu);
+  s->W_alpha = d->W_alpha;
+  s->W_x = d->W_x;
+  s->gamma_d = d->gamma_d;
+  s->safety_by_prob = d->weight_safety_by_prob ? 1 : 0;
+  const std::vector<double>* arrs[] = {&s->A, &s->B, &s->Gd, &s->E, &s->Ed, &s->umin, &s->umax,
+                                       &s->xmin, &s->xmax, &s->xs, &s->alpha1, &s->Wu};
+  bool fin = std::isfinite(s->W_alpha) && std::isfinite(s->W_x) && std::isfinite(s->gamma_d);
+  for (auto* a : arrs) fin = fin && all_finite(a->data(), a->size());
+  if (!fin) {
+    delete s;
+    return set_error(SMPC_ENAN, "NaN or Inf in the system description");
+  }
+  for (int j = 0; j < nu; ++j)
+    if (s->umin[j] > s->umax[j]) {
+      delete s;
+      return set_error(SMPC_EINVAL, "umin > umax at %d", j);
+    }
+  for (int i = 0; i < nx; ++i)
+    if (s->xmin[i] > s->xmax[i]) {
+      delete s;
+      return set_error(SMPC_EINVAL, "xmin > xmax at %d", i);
+    }
+  if (s->W_x < 0 || s->gamma_d < 0) {
+    delete s;
+    return set_error(SMPC_EINVAL, "W_x and gamma_d must be >= 0");
+  }
+  int rc = sys_factor(s);
+  if (rc < 0) {
+    delete s;
+    return rc;
+  }
+  if (lds_bytes_backward(nx, nu, sizeof(double)) > 160 * 1024) {
+    delete s;
+    return set_error(SMPC_EDIM, "system too large for the LDS-resident factor");
+  }
+  rc = sys_upload<double>(s, s->d64);
+  if (rc < 0) {
+    sys_free(ctx, s->d64);
+    delete s;
+    return rc;
+  }
+  ctx->n_sys++;
+  *out = s;
+  return SMPC_OK;
+}
+
+int smpc_sys_destroy(smpc_sys* s) {
+  if (!s) return SMPC_OK;
+  if (s->n_trees > 0) return set_error(SMPC_EINVAL, "system still has %d trees", s->n_trees);
+  smpc_ctx* ctx = s->ctx;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->batch_plan) {
+    plan_free(ctx, ctx->batch_plan);
+    ctx->batch_plan = nullptr;
+  }
+  sys_free(ctx, s->d64);
+  sys_free(ctx, s->d32);
+  ctx->n_sys--;
+  delete s;
+  return SMPC_OK;
+}
+
+int smpc_tree_create(smpc_sys* sys, int N, int M, const int32_t* stage, const int32_t* parent,
+                     const double* prob, smpc_tree** out) {
+  if (!sys || !stage || !parent || !prob || !out) return set_error(SMPC_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (N < 1 || M < 1) return set_error(SMPC_EINVAL, "need N >= 1 and M >= 1 (got N=%d, M=%d)", N, M);
+  if (stage[0] != 0 || parent[0] != -1) return set_error(SMPC_EPROB, "node 0 must be the root");
+  if (!(std::fabs(prob[0] - 1.0) <= 1e-12)) return set_error(SMPC_EPROB, "root probability must be 1");
+  std::vector<int> nch(M, 0);
+  std::vector<double> csum(M, 0.0);
+  for (int n = 0; n < M; ++n) {
+    if (!std::isfinite(prob[n])) return set_error(SMPC_ENAN, "probability %d is not finite", n);
+    if (!(prob[n] > 0.0)) return set_error(SMPC_EPROB, "probability %d is not positive", n);
+    if (stage[n] < 0 || stage[n] >= N) return set_error(SMPC_EPROB, "stage %d out of range", n);
+    if (n > 0) {
+      if (stage[n] < stage[n - 1]) return set_error(SMPC_EPROB, "nodes must be stage-sorted (node %d)", n);
+      const int a = parent[n];
+      if (a < 0 || a >= n) return set_error(SMPC_EPROB, "parent of node %d must be an earlier node", n);
+      if (stage[a] != stage[n] - 1) return set_error(SMPC_EPROB, "parent of node %d is not one stage up", n);
+      nch[a]++;
+      csum[a] += prob[n];
+    }
+  }
+  for (int n = 0; n < M; ++n) {
+    if (stage[n] < N - 1 && nch[n] == 0) return set_error(SMPC_EPROB, "node %d at stage %d has no child", n, stage[n]);
+    if (nch[n] > 0 && std::fabs(csum[n] - prob[n]) > 1e-9 * prob[n])
+      return set_error(SMPC_EPROB, "children of node %d do not sum to its probability", n);
+  }
+  if (stage[M - 1] != N - 1) return set_error(SMPC_EPROB, "the last stage must be N-1");
+  smpc_tree* t = new (std::nothrow) smpc_tree();
+  if (!t) return set_error(SMPC_ENOMEM, "host allocation failed");
+  t->sys = sys;
+  t->N = N;
+  t->M = M;
+  t->stage.assign(stage, stage + M);
+  t->parent.assign(parent, parent + M);
+  t->prob.assign(prob, prob + M);
+  // children lists
+  std::vector<int> cstart(M + 1, 0), clist(M > 1 ? M - 1 : 0);
+  for (int n = 0; n < M; ++n) cstart[n + 1] = cstart[n] + nch[n];
+  {
+    std::vector<int> fill(cstart.begin(), cstart.end() - 1);
+    for (int n = 1; n < M; ++n) clist[fill[parent[n]]++] = n;
+  }
+  // chains, breadth-first; internal order = chain-major
+  t->perm.reserve(M);
+  std::deque<std::pair<int, int>> queue;  // (start node, parent chain)
+  queue.push_back({0, -1});
+  while (!queue.empty()) {
+    auto [start, pc] = queue.front();
+    queue.pop_front();
+    ChainDesc cd{};
+    cd.first = (int32_t)t->perm.size();
+    cd.parent = pc;
+    int nd = start;
+    int len = 0;
+    while (true) {
+      t->perm.push_back(nd);
+      ++len;
+      if (nch[nd] != 1) break;
+      nd = clist[cstart[nd]];
+    }
+    cd.len = len;
+    const int id = (int)t->chains.size();
+    cd.child_count = nch[nd];
+    cd.child_begin = (int32_t)(t->chains.size() + queue.size() + 1);
+    for (int k = 0; k < nch[nd]; ++k) queue.push_back({clist[cstart[nd] + k], id});
+    t->chains.push_back(cd);
+  }
+  t->iperm.assign(M, 0);
+  for (int i = 0; i < M; ++i) t->iperm[t->perm[i]] = i;
+  // heights
+  int H = 0;
+  for (int c = (int)t->chains.size() - 1; c >= 0; --c) {
+    ChainDesc& cd = t->chains[c];
+    int h = 0;
+    for (int k = 0; k < cd.child_count; ++k) h = std::max(h, t->chains[cd.child_begin + k].height + 1);
+    cd.height = h;
+    H = std::max(H, h + 1);
+  }
+  t->n_levels = H;
+  t->level_chains.assign(H, {});
+  for (int c = 0; c < (int)t->chains.size(); ++c) t->level_chains[t->chains[c].height].push_back(c);
+  for (auto& l : t->level_chains)
+    std::stable_sort(l.begin(), l.end(), [&](int a, int b) { return t->chains[a].len > t->chains[b].len; });
+  // device state
+  smpc_ctx* ctx = sys->ctx;
+  const size_t C = t->chains.size();
+  int rc = ctx->alloc(t->cstat, sizeof(double) * kStat * C);
+  if (rc >= 0) rc = ctx->alloc(t->st, sizeof(TreeState));
+  if (rc >= 0) rc = ctx->alloc(t->chains_dev, sizeof(ChainDesc) * C);
+  if (rc >= 0) {
+    hipError_t e = hipMemcpyAsync(t->chains_dev.ptr, t->chains.data(), sizeof(ChainDesc) * C, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(t->cstat.ptr, 0, sizeof(double) * kStat * C, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(t->st.ptr, 0, sizeof(TreeState), ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) rc = set_error(SMPC_EDEVICE, "tree upload failed: %s", hipGetErrorString(e));
+  }
+  if (rc >= 0) rc = tree_alloc<double>(t);
+  if (rc < 0) {
+    tree_free(ctx, t->b64);
+    ctx->release(t->cstat);
+    ctx->release(t->st);
+    ctx->release(t->chains_dev);
+    delete t;
+    return rc;
+  }
+  sys->n_trees++;
+  *out = t;
+  return SMPC_OK;
+}
+
+int smpc_tree_destroy(smpc_tree* t) {
+  if (!t) return SMPC_OK;
+  smpc_ctx* ctx = t->sys->ctx;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->batch_plan) {
+    plan_free(ctx, ctx->batch_plan);
+    ctx->batch_plan = nullptr;
+  }
+  if (t->plan) plan_free(ctx, t->plan);
+  tree_free(ctx, t->b64);
+  tree_free(ctx, t->b32);
+  ctx->release(t->cstat);
+  ctx->release(t->st);
+  ctx->release(t->chains_dev);
+  t->sys->n_trees--;
+  delete t;
+  return SMPC_OK;
+}
+
+int smpc_tree_info(smpc_tree* t, int* M, int* N, int* n_chains, int* n_levels) {
+  if (!t) return set_error(SMPC_EINVAL, "tree is NULL");
+  if (M) *M = t->M;
+  if (N) *N = t->N;
+  if (n_chains) *n_chains = (int)t->chains.size();
+  if (n_levels) *n_levels = t->n_levels;
+  return SMPC_OK;
+}
+
+int smpc_tree_set_data(smpc_tree* t, const double* d, const double* alpha2) {
+  if (!t) return set_error(SMPC_EINVAL, "tree is NULL");
+  const smpc_sys* s = t->sys;
+  if (s->nd > 0 && !d) return set_error(SMPC_EINVAL, "d is NULL");
+  if (d && !all_finite(d, (size_t)t->M * s->nd)) return set_error(SMPC_ENAN, "NaN or Inf in d");
+  if (alpha2 && !all_finite(alpha2, (size_t)t->N * s->nu)) return set_error(SMPC_ENAN, "NaN or Inf in alpha2");
+  std::vector<double> zero;
+  if (!d) {
+    zero.assign((size_t)t->M * std::max(1, s->nd), 0.0);
+    d = zero.data();
+  }
+  tree_cost_update(t, d, alpha2);
+  SMPC_TRY(tree_upload_data<double>(t));
+  if (t->b32.allocated) SMPC_TRY(tree_upload_data<float>(t));
+  t->has_data = true;
+  return SMPC_OK;
+}
+
+int smpc_factor(smpc_tree* t, const smpc_factor_opts* o) {
+  if (!t) return set_error(SMPC_EINVAL, "tree is NULL");
+  smpc_factor_opts def{};
+  if (!o) o = &def;
+  smpc_sys* s = t->sys;
+  smpc_ctx* ctx = s->ctx;
+  const int M = t->M, nx = s->nx, nu = s->nu, D = 2 * nx + nu;
+  // dual scaling
+  if (o->scale) {
+    if (!all_finite(o->scale, (size_t)M * 3)) return set_error(SMPC_ENAN, "NaN or Inf in scale");
+    t->scale.assign((size_t)M * 3, 1.0);
+    for (int n = 0; n < M; ++n)
+      for (int b = 0; b < 3; ++b) {
+        const double v = o->scale[(size_t)n * 3 + b];
+        if (!(v > 0.0)) return set_error(SMPC_EINVAL, "scale must be positive");
+        t->scale[(size_t)t->iperm[n] * 3 + b] = v;
+      }
+  } else if (o->precond == 1) {
+    std::vector<double> diag;
+    single_branch_precond(s, t->N, diag);
+    t->scale.assign((size_t)M * 3, 1.0);
+    for (int n = 0; n < M; ++n)
+      for (int b = 0; b < 3; ++b) {
+        const double dd = diag[(size_t)t->stage[n] * 3 + b];
+        t->scale[(size_t)t->iperm[n] * 3 + b] = dd > 0.0 ? std::sqrt(t->prob[n] / dd) : 1.0;
+      }
+  } else if (o->precond == 0) {
+    t->scale.clear();
+  } else {
+    return set_error(SMPC_EINVAL, "precond must be 0 or 1");
+  }
+  SMPC_TRY(tree_upload_scale<double>(t));
+  SMPC_TRY(tree_alloc<double>(t));
+  if (t->b32.allocated) {
+    SMPC_TRY(tree_upload_scale<float>(t));
+    SMPC_TRY(tree_alloc<float>(t));
+  }
+  if (t->plan) {
+    plan_free(ctx, t->plan);
+    t->plan = nullptr;
+  }
+  if (ctx->batch_plan) {
+    plan_free(ctx, ctx->batch_plan);
+    ctx->batch_plan = nullptr;
+  }
+  if (o->lambda_override > 0.0) {
+    if (!std::isfinite(o->lambda_override)) return set_error(SMPC_EINVAL, "lambda_override not finite");
+    t->lambda = o->lambda_override;
+    t->lmax = 1.0 / o->lambda_override;
+    t->factored = true;
+    return SMPC_OK;
+  }
+  // power iteration on the (scaled) dual Hessian, float64 on the device
+  SMPC_TRY(ensure_single_plan(t, false));
+  std::vector<double> h((size_t)M * D);
+  double nrm = 0.0;
+  for (size_t i = 0; i < h.size(); ++i) {
+    h[i] = 0.5 + (double)(splitmix(i + 0x5eedULL) >> 11) * (1.0 / 9007199254740992.0);
+    nrm += h[i] * h[i];
+  }
+  HIP_TRY(hipMemcpyAsync(t->b64.y[0].ptr, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, ctx->stream));
+  TreeState st{};
+  st.iter = 0;
+  st.done = 0;
+  st.max_iter = 1 << 30;
+  st.check_every = 1;
+  st.lambda = 1.0;
+  st.in_scale = 1.0 / std::sqrt(nrm);
+  SMPC_TRY(write_state(t, st));
+  const int iters = o->power_iters > 0 ? o->power_iters : 200;
+  for (int k = 0; k < iters; ++k) SMPC_TRY(enqueue_iteration<double>(ctx, s, t->plan, kModePower, true));
+  SMPC_TRY(read_state(t, &st));
+  if (!(st.lmax_est > 0.0) || !std::isfinite(st.lmax_est))
+    return set_error(SMPC_EDEVICE, "power iteration failed (estimate %g)", st.lmax_est);
+  t->lmax = st.lmax_est;
+  t->lambda = 1.0 / (st.lmax_est * 1.02);
+  t->factored = true;
+  return SMPC_OK;
+}
+
+int smpc_tree_get_factor(smpc_tree* t, double* lambda, double* scale) {
+  if (!t) return set_error(SMPC_EINVAL, "tree is NULL");
+  if (!t->factored) return set_error(SMPC_ENOTFACTORED, "smpc_factor not called");
+  if (lambda) *lambda = t->lambda;
+  if (scale) {
+    for (int n = 0; n < t->M; ++n)
+      for (int b = 0; b < 3; ++b)
+        scale[(size_t)n * 3 + b] = t->scale.empty() ? 1.0 : t->scale[(size_t)t->iperm[n] * 3 + b];
+  }
+  return SMPC_OK;
+}
+
+int smpc_solve(smpc_tree* t, const double* p, const double* q, const smpc_solve_opts* o, smpc_result* res) {
+  SMPC_TRY(tree_check_ready(t, true));
+  SMPC_TRY(check_opts(o));
+  if (!p || !q) return set_error(SMPC_EINVAL, "p or q is NULL");
+  if (!all_finite(p, t->sys->nx) || !all_finite(q, t->sys->nu)) return set_error(SMPC_ENAN, "NaN or Inf in p or q");
+  if (o->warm_start == 2) {
+    const size_t n = (size_t)t->M * (2 * t->sys->nx + t->sys->nu);
+    if (!all_finite(o->y0, n) || (o->y_prev0 && !all_finite(o->y_prev0, n)))
+      return set_error(SMPC_ENAN, "NaN or Inf in the warm start");
+  }
+  const bool need32 = o->precision == 32 && o->max_iter > o->polish_iters;
+  if (need32) SMPC_TRY(prepare32(t));
+  SMPC_TRY(ensure_single_plan(t, need32));
+  smpc_result tmp{};
+  smpc_result* r = res ? res : &tmp;
+  SMPC_TRY(solve_plan(t->plan, &p, &q, o, r));
+  if (r->status == SMPC_EDIVERGED)
+    set_error(SMPC_EDIVERGED, "iteration diverged (residual non-finite or above 1e300) after %d iterations",
+              r->iterations);
+  return r->status;
+}
+
+int smpc_solve_batch(smpc_tree* const* trees, int n, const double* const* p, const double* const* q,
+                     const smpc_solve_opts* o, smpc_result* res) {
+  if (!trees || n < 1 || !p || !q) return set_error(SMPC_EINVAL, "bad batch arguments");
+  SMPC_TRY(check_opts(o));
+  smpc_sys* sys = trees[0] ? trees[0]->sys : nullptr;
+  for (int k = 0; k < n; ++k) {
+    SMPC_TRY(tree_check_ready(trees[k], true));
+    if (trees[k]->sys != sys) return set_error(SMPC_EINVAL, "all trees of a batch must share one system");
+    if (!p[k] || !q[k]) return set_error(SMPC_EINVAL, "p[%d] or q[%d] is NULL", k, k);
+    if (!all_finite(p[k], sys->nx) || !all_finite(q[k], sys->nu)) return set_error(SMPC_ENAN, "NaN or Inf in p/q %d", k);
+    for (int j = 0; j < k; ++j)
+      if (trees[j] == trees[k]) return set_error(SMPC_EINVAL, "tree %d appears twice in the batch", k);
+  }
+  smpc_ctx* ctx = sys->ctx;
+  const bool need32 = o->precision == 32 && o->max_iter > o->polish_iters;
+  if (need32)
+    for (int k = 0; k < n; ++k) SMPC_TRY(prepare32(trees[k]));
+  std::vector<smpc_tree*> tv(trees, trees + n);
+  Plan* plan = ctx->batch_plan;
+  if (!plan || plan->trees != tv || (need32 && !plan->has32)) {
+    if (plan) plan_free(ctx, plan);
+    ctx->batch_plan = nullptr;
+    SMPC_TRY(plan_build(ctx, tv, need32, &ctx->batch_plan));
+    plan = ctx->batch_plan;
+  }
+  std::vector<smpc_result> tmp(n);
+  smpc_result* r = res ? res : tmp.data();
+  SMPC_TRY(solve_plan(plan, p, q, o, r));
+  int worst = SMPC_OK;
+  for (int k = 0; k < n; ++k) {
+    if (r[k].status < 0) worst = r[k].status;
+    else if (worst == SMPC_OK && r[k].status > 0) worst = r[k].status;
+  }
+  if (worst == SMPC_EDIVERGED) set_error(SMPC_EDIVERGED, "at least one tree of the batch diverged");
+  return worst;
+}
+
+int smpc_solve_step(smpc_tree* t, const double* p, const double* q, const double* w, int precision, double* x,
+                    double* u) {
+  SMPC_TRY(tree_check_ready(t, false));
+  if (!t->has_data) return set_error(SMPC_ENOTFACTORED, "smpc_tree_set_data not called");
+  if (!p || !q || !w) return set_error(SMPC_EINVAL, "NULL argument");
+  if (precision != 64 && precision != 32) return set_error(SMPC_EINVAL, "precision must be 32 or 64");
+  smpc_sys* s = t->sys;
+  smpc_ctx* ctx = s->ctx;
+  const int M = t->M, nx = s->nx, nu = s->nu, D = 2 * nx + nu;
+  if (!all_finite(w, (size_t)M * D)) return set_error(SMPC_ENAN, "NaN or Inf in w");
+  const bool use32 = precision == 32;
+  if (use32) SMPC_TRY(prepare32(t));
+  SMPC_TRY(ensure_single_plan(t, use32));
+  SMPC_TRY(ctx->ensure_ctab(4));
+  TreeState st{};
+  st.iter = 0;
+  st.done = 0;
+  st.max_iter = 1;
+  st.check_every = 1;
+  st.lambda = 1.0;
+  st.in_scale = 1.0;
+  SMPC_TRY(write_state(t, st));
+  // w in internal order, unscaled (the solve-step mode ignores the scaling)
+  auto put = [&](auto tag) -> int {
+    using T = decltype(tag);
+    std::vector<T> h((size_t)M * D);
+    for (int in = 0; in < M; ++in) {
+      const int n = t->perm[in];
+      for (int k = 0; k < D; ++k) h[(size_t)in * D + k] = (T)w[(size_t)n * D + k];
+    }
+    HIP_TRY(hipMemcpyAsync(treebuf<T>(t).y[0].ptr, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SMPC_OK;
+  };
+  if (use32) {
+    SMPC_TRY(upload_root<float>(t, p, q));
+    SMPC_TRY(put(float{}));
+    SMPC_TRY(enqueue_iteration<float>(ctx, s, t->plan, kModeSolve, false));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    SMPC_TRY(download_primal<float>(t, x, u, nullptr));
+  } else {
+    SMPC_TRY(upload_root<double>(t, p, q));
+    SMPC_TRY(put(double{}));
+    SMPC_TRY(enqueue_iteration<double>(ctx, s, t->plan, kModeSolve, false));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    SMPC_TRY(download_primal<double>(t, x, u, nullptr));
+  }
+  return SMPC_OK;
+}
+
+int smpc_ctx_set_profiling(smpc_ctx* ctx, int enable) {
+  if (!ctx) return set_error(SMPC_EINVAL, "ctx is NULL");
+  ctx->flush_profile();
+  ctx->profiling = enable != 0;
+  return SMPC_OK;
+}
+
+int smpc_ctx_kernel_stats(smpc_ctx* ctx, smpc_kernel_stat* out, int cap, int* n) {
+  if (!ctx) return set_error(SMPC_EINVAL, "ctx is NULL");
+  ctx->flush_profile();
+  int k = 0;
+  for (auto& kv : ctx->stats) {
+    if (out && k < cap) {
+      std::memset(out[k].name, 0, sizeof(out[k].name));
+      std::strncpy(out[k].name, kv.first.c_str(), sizeof(out[k].name) - 1);
+      out[k].launches = kv.second.first;
+      out[k].total_ms = kv.second.second;
+    }
+    ++k;
+  }
+  if (n) *n = k;
+  return SMPC_OK;
+}
+
+int smpc_ctx_reset_stats(smpc_ctx* ctx) {
+  if (!ctx) return set_error(SMPC_EINVAL, "ctx is NULL");
+  ctx->flush_profile();
+  ctx->stats.clear();
+  return SMPC_OK;
+}
+
+}  // extern "C"

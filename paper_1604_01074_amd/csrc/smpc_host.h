@@ -1,0 +1,144 @@
+// Host-side objects behind the C ABI handles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/smpc.h"
+#include "smpc_internal.h"
+
+namespace smpc {
+
+// ----------------------------------------------------------------- errors
+int set_error(int code, const char* fmt, ...);
+
+// ----------------------------------------------------------------- dense FP64 helpers
+// Row-major n x n Cholesky (lower factor in place).  False if a pivot is not
+// positive relative to the largest diagonal entry.
+bool cholesky(std::vector<double>& a, int n);
+// Solve (L L') x = b in place for a factor from cholesky().
+void chol_solve(const std::vector<double>& l, int n, double* b);
+
+struct Csr {
+  std::vector<int32_t> rp, ci;
+  std::vector<double> v;
+};
+Csr dense_to_csr(const double* a, int rows, int cols);
+Csr dense_to_csr_transposed(const double* a, int rows, int cols);
+
+// ----------------------------------------------------------------- device buffers
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+}  // namespace smpc
+
+struct smpc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0;
+  size_t used = 0;
+  int n_sys = 0;
+  // c_nu = theta_nu (1/theta_{nu-1} - 1) for nu = 0..ctab_len-1
+  double* ctab = nullptr;
+  int ctab_len = 0;
+  // profiling
+  bool profiling = false;
+  std::vector<smpc::ProfRec> prof;
+  std::vector<hipEvent_t> ev_pool;
+  std::map<std::string, std::pair<int, double>> stats;
+  // cached batch launch plan
+  struct Plan* batch_plan = nullptr;
+
+  int alloc(smpc::DevBuf& b, size_t bytes);
+  void release(smpc::DevBuf& b);
+  int ensure_ctab(int n);
+  hipEvent_t get_event();
+  void flush_profile();
+};
+
+template <typename T>
+struct SysBuffers {
+  smpc::DevBuf P, b_rp, b_ci, b_v, bt_rp, bt_ci, bt_v, a_rp, a_ci, a_v, at_rp, at_ci, at_v;
+  smpc::DevBuf umin, umax, xmin, xmax, xs;
+  smpc::SysDev<T> view{};
+};
+
+struct smpc_sys {
+  smpc_ctx* ctx = nullptr;
+  int nx = 0, nu = 0, nd = 0, ne = 0;
+  std::vector<double> A, B, Gd, E, Ed, umin, umax, xmin, xmax, xs, alpha1, Wu;
+  double W_alpha = 0, W_x = 0, gamma_d = 0;
+  int safety_by_prob = 1;
+  // tree-independent factor products
+  std::vector<double> P;   // nu x nu:  L (L' Wu L)^{-1} L'
+  std::vector<double> Mu;  // nu x nd:  uhat = Mu d (minimum-norm)
+  smpc::Csr Bc, Btc, Ac, Atc;
+  int a_identity = 0;
+  SysBuffers<double> d64;
+  SysBuffers<float> d32;
+  bool has32 = false;
+  int n_trees = 0;
+};
+
+template <typename T>
+struct TreeBuffers {
+  smpc::DevBuf y[3], beta, uhat, e, pi, scale, p, du, z, ctopQ, ctopR, cbotX, cbotU;
+  smpc::TreeDev<T> view{};
+  bool allocated = false;
+};
+
+struct smpc_tree {
+  smpc_sys* sys = nullptr;
+  int N = 0, M = 0;
+  std::vector<int32_t> stage, parent;
+  std::vector<double> prob;
+  // internal (chain-major) order
+  std::vector<int32_t> perm;   // internal -> caller index
+  std::vector<int32_t> iperm;  // caller -> internal index
+  std::vector<smpc::ChainDesc> chains;
+  int n_levels = 0;
+  std::vector<std::vector<int32_t>> level_chains;  // chains of each height, longest first
+  // float64 host copies of the per-node data, internal order
+  std::vector<double> beta0;  // beta with q = 0 (root term added per solve)
+  std::vector<double> uhat, e, pi;
+  std::vector<double> scale;  // M x 3 or empty
+  bool has_data = false;
+  bool factored = false;
+  double lambda = 0.0;
+  double lmax = 0.0;
+  // device
+  TreeBuffers<double> b64;
+  TreeBuffers<float> b32;
+  smpc::DevBuf cstat, st, chains_dev;
+  struct Plan* plan = nullptr;  // single-tree launch plan
+};
+
+// Launch plan: the work lists of one set of trees solved together.
+struct Plan {
+  std::vector<smpc_tree*> trees;
+  int H = 0;
+  std::vector<int> lvl_off, lvl_cnt;
+  smpc::DevBuf items, td64, td32, refs, done;
+  std::vector<int32_t> done_host;
+  bool has32 = false;
+};
+
+namespace smpc {
+// smpc_setup.cpp
+int sys_factor(smpc_sys* s);
+void tree_cost_update(smpc_tree* t, const double* d, const double* alpha2);
+void root_beta(const smpc_tree* t, const double* q, std::vector<double>& out);
+void single_branch_precond(const smpc_sys* s, int N, std::vector<double>& diag);  // N x 3
+}  // namespace smpc

@@ -1,0 +1,136 @@
+// Internal data structures shared by the host library and the HIP kernels.
+//
+// Device layout (all node arrays in the library's internal "chain-major"
+// order: the nodes of chain 0 top to bottom, then chain 1, ...; chains are
+// numbered breadth-first so the child chains of a chain are consecutive):
+//
+//   y[3]    M x D      rotating dual iterates y^nu, y^{nu-1}, y^{nu+1}
+//                      (D = 2 nx + nu; block order sigma~ | zeta~ | psi~)
+//   beta    M x nu     linear cost of the input in u-space (see smpc_setup.cpp)
+//   uhat    M x nu     particular solution of E u + Ed d = 0
+//   e       M x nx     B uhat + Gd d
+//   pi      M          node probability
+//   scale   M x 3      optional dual scaling per (node, block)
+//   du      M x nu     backward-pass output: input increment of the node
+//   z       M x (nx+nu)  primal iterate (x_n, u_n), written on check steps
+//   ctopQ/ctopR  per chain: state / input cost-to-go coefficients of the
+//                chain's top node, read by the parent chain's bottom node
+//   cbotX/cbotU  per chain: state / input-increment sum of the bottom node,
+//                read by the child chains' top nodes
+//   cstat   per chain: 4 float64 reduction partials
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace smpc {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kStat = 4;         // float64 partials per chain
+
+enum Mode : int {
+  kModeAPG = 0,     // one APG iteration (extrapolate, solve step, prox, update)
+  kModeSolve = 1,   // solve step only at w = y[0]; writes z
+  kModePower = 2,   // linear part of the dual gradient, for the power iteration
+};
+
+struct ChainDesc {
+  int32_t first;        // internal index of the top node
+  int32_t len;          // number of nodes
+  int32_t parent;       // parent chain (-1 for the root chain)
+  int32_t child_begin;  // first child chain
+  int32_t child_count;  // number of child chains (0 for a leaf chain)
+  int32_t height;       // 0 for leaf chains, 1 + max over children otherwise
+};
+
+struct WorkItem {
+  int32_t tree;   // slot in the launch's tree table
+  int32_t chain;  // chain id within that tree
+};
+
+// Per-tree iteration state, resident on the device.  Written by the host
+// before a solve and by k_iter_end between iterations.
+struct TreeState {
+  int32_t iter;         // index nu of the iteration being run
+  int32_t done;         // 1 -> kernels skip this tree
+  int32_t max_iter;     // stop after this many iterations
+  int32_t check_every;  // residual test period
+  int32_t status;       // 0 converged, 1 max_iter, -9 diverged
+  int32_t iters_done;   // iterations when the tree stopped
+  int32_t pad0, pad1;
+  double tol;
+  double lambda;
+  double r_p;           // last ||Hz - t||_inf
+  double hzt;           // last max(||Hz||_inf, ||t||_inf)
+  double in_scale;      // power iteration: 1 / ||g_k||
+  double lmax_est;      // power iteration: Rayleigh quotient
+};
+
+struct IterRef {
+  TreeState* st;
+  const double* cstat;
+  int32_t* done_out;   // done flag of tree `slot`, gathered for one host read
+  int32_t n_chains;
+  int32_t slot;
+};
+
+template <typename T>
+struct SysDev {
+  int32_t nx, nu, D;
+  int32_t a_identity;
+  const T* P;                                          // nu x nu, symmetric
+  const int32_t* b_rp; const int32_t* b_ci; const T* b_v;     // B  (CSR)
+  const int32_t* bt_rp; const int32_t* bt_ci; const T* bt_v;  // B' (CSR)
+  const int32_t* a_rp; const int32_t* a_ci; const T* a_v;     // A  (CSR)
+  const int32_t* at_rp; const int32_t* at_ci; const T* at_v;  // A' (CSR)
+  const T* umin; const T* umax;
+  const T* xmin; const T* xmax; const T* xs;
+  double W_x, gamma_d;
+  int32_t safety_by_prob;
+  int32_t pad;
+};
+
+template <typename T>
+struct TreeDev {
+  T* y[3];
+  const T* beta;
+  const T* uhat;
+  const T* e;
+  const T* pi;
+  const T* scale;   // nullptr -> no scaling
+  const T* p;       // nx: state of the root's parent
+  T* du;
+  T* z;
+  T* ctopQ;
+  T* ctopR;
+  T* cbotX;
+  T* cbotU;
+  double* cstat;
+  const ChainDesc* chains;
+  TreeState* st;
+  int32_t n_chains;
+  int32_t M;
+};
+
+// Kernel launchers (smpc_kernels.hip).  `items` lists the chains of one
+// level across all trees of the launch; `trees` is a device table.
+template <typename T>
+hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
+                           int n_items, const double* ctab, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
+                          int n_items, const double* ctab, int mode, hipStream_t s);
+// One workgroup per tree: folds the chain partials, applies the stop test
+// (or the power-iteration normalisation) and advances the iteration index.
+// `refs` is a device array of n_trees IterRef.
+hipError_t launch_iter_end_refs(const void* refs, int n_trees, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_convert_dual(const double* src, T* dst, size_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s);
+
+size_t lds_bytes_backward(int nx, int nu, size_t elem);
+size_t lds_bytes_forward(int nx, int nu, size_t elem);
+
+}  // namespace smpc

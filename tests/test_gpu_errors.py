@@ -1,0 +1,115 @@
+"""Error paths of the C ABI (host-side validation; every kernel that runs in
+these tests runs on valid data and exits normally)."""
+
+import numpy as np
+import pytest
+
+import dwn_synth as ds
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1604_01074_amd import smpc
+
+    return smpc
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    h = S.smpc_ctx_create(0)
+    yield h
+    S.smpc_ctx_destroy(h)
+
+
+def _code(S, fn, *a, **k):
+    with pytest.raises(S.SmpcError) as ei:
+        fn(*a, **k)
+    return ei.value.code
+
+
+def test_system_validation(S, ctx):
+    base = ds.tiny_tank_system(0)
+    bad = dict(base, Wu=-np.eye(3))
+    assert _code(S, S.smpc_sys_create, ctx, bad) == S.ENOTSPD
+    bad = dict(base, Wu=np.array([[1.0, 0.5, 0], [0.0, 1.0, 0], [0, 0, 1.0]]))
+    assert _code(S, S.smpc_sys_create, ctx, bad) == S.ENOTSPD
+    A = base["A"].copy()
+    A[0, 0] = np.nan
+    assert _code(S, S.smpc_sys_create, ctx, dict(base, A=A)) == S.ENAN
+    assert _code(S, S.smpc_sys_create, ctx, dict(base, umin=np.full(3, 6.0))) == S.EINVAL
+    r = ds.random_dense_system(0, nx=3, nu=5, nd=2, ne=2)
+    E = r["E"].copy()
+    E[1] = E[0]
+    assert _code(S, S.smpc_sys_create, ctx, dict(r, E=E)) == S.ERANK
+    big = ds.random_dense_system(0, nx=3, nu=140, nd=2, ne=1)
+    assert _code(S, S.smpc_sys_create, ctx, big) == S.EDIM
+
+
+def test_tree_validation(S, ctx):
+    inst = ds.tiny_instance()
+    s = S.smpc_sys_create(ctx, inst.sys)
+    t = inst.tree
+    try:
+        par = t["parent"].copy()
+        par[3] = 4  # later node as parent
+        assert _code(S, S.smpc_tree_create, s, t["N"], t["stage"], par, t["prob"]) == S.EPROB
+        pr = t["prob"].copy()
+        pr[3] *= 1.1  # children no longer sum to the parent
+        assert _code(S, S.smpc_tree_create, s, t["N"], t["stage"], t["parent"], pr) == S.EPROB
+        pr = t["prob"].copy()
+        pr[5] = np.nan
+        assert _code(S, S.smpc_tree_create, s, t["N"], t["stage"], t["parent"], pr) == S.ENAN
+        # a leaf before the last stage
+        assert _code(S, S.smpc_tree_create, s, t["N"] + 1, t["stage"], t["parent"], t["prob"]) == S.EPROB
+        # empty tree
+        assert _code(S, S.smpc_tree_create, s, t["N"], np.zeros(0), np.zeros(0), np.zeros(0)) == S.EINVAL
+        tr = S.smpc_tree_create(s, t["N"], t["stage"], t["parent"], t["prob"])
+        try:
+            dims = (inst.M, 4, 3)
+            assert _code(S, S.smpc_solve, tr, inst.p, inst.q, dims=dims) == S.ENOTFACTORED
+            d = inst.d.copy()
+            d[0, 0] = np.inf
+            assert _code(S, S.smpc_tree_set_data, tr, d) == S.ENAN
+            S.smpc_tree_set_data(tr, inst.d)
+            S.smpc_factor(tr, lambda_override=1e-3)
+            assert _code(S, S.smpc_solve, tr, inst.p, inst.q, dims=dims, max_iter=0) == S.EINVAL
+            assert _code(S, S.smpc_solve, tr, inst.p, inst.q, dims=dims, precision=16) == S.EINVAL
+            p = inst.p.copy()
+            p[1] = np.nan
+            assert _code(S, S.smpc_solve, tr, p, inst.q, dims=dims) == S.ENAN
+            # the system cannot go while a tree uses it
+            assert _code(S, S.smpc_sys_destroy, s) == S.EINVAL
+        finally:
+            S.smpc_tree_destroy(tr)
+    finally:
+        S.smpc_sys_destroy(s)
+
+
+def test_hbm_budget(S):
+    h = S.smpc_ctx_create(0, None, 64 * 1024)
+    try:
+        inst = ds.barcelona_instance(N=6, branching=(3, 2))
+        assert _code(S, S.smpc_sys_create, h, inst.sys) == S.ENOMEM
+    finally:
+        S.smpc_ctx_destroy(h)
+
+
+def test_max_iter_status_and_divergence_flag(S, ctx):
+    inst = ds.tiny_instance()
+    s = S.smpc_sys_create(ctx, inst.sys)
+    tr = S.smpc_tree_create(s, inst.N, inst.tree["stage"], inst.tree["parent"], inst.tree["prob"])
+    try:
+        S.smpc_tree_set_data(tr, inst.d)
+        S.smpc_factor(tr, power_iters=100)
+        r = S.smpc_solve(tr, inst.p, inst.q, dims=(inst.M, 4, 3), tol=1e-12, max_iter=30)
+        assert r["status"] == S.MAX_ITER and r["iterations"] == 30
+        # a step far above 1/L makes the iteration blow up: reported, not hidden
+        S.smpc_factor(tr, lambda_override=1e6)
+        r = S.smpc_solve(tr, inst.p, inst.q, dims=(inst.M, 4, 3), tol=1e-3, max_iter=3000)
+        assert r["status"] in (S.EDIVERGED, S.MAX_ITER)
+        assert np.all(np.isfinite(r["u0"])) or r["status"] == S.EDIVERGED
+    finally:
+        S.smpc_tree_destroy(tr)
+        S.smpc_sys_destroy(s)
