@@ -8,8 +8,9 @@ Workload recipes (all seeded, all synthetic):
   component, ``p = 5``, ``q = 1``.
 * ``barcelona_instance``: Barcelona-shaped system (63/114/88/17), ``N = 24``,
   branching [7, 7, 7] (343 scenarios, 7260 nodes), log-normal demands around
-  a 24-periodic profile with 10 % spread, feasible junction demands, hourly
-  pumping tariff.
+  a 24-periodic profile with 10 % spread (junction consumption within the
+  junction's inflow capacity), hourly pumping tariff, ``p = 0.6 x_max``,
+  ``q = 0.3 u_max``.
 * ``batch_instances``: 64 trees (seeds 100..163) on the Barcelona-shaped
   system, horizons in {12, 18, 24}, scenario counts in {16, 64, 125, 343, 512}.
 * ``random_small_instance``: small dense systems with general ``A`` and
@@ -74,26 +75,29 @@ def pumping_cost(sys: dict, N: int, start_hour: int = 0) -> np.ndarray:
 def barcelona_demands(sys: dict, tree: dict, rng: np.random.Generator, start_hour: int = 0):
     """Node demands for a Barcelona-shaped system.
 
-    Tank demands: ``dhat_k(j) = b_k (1 + 0.3 sin(2 pi (j + phi_k) / 24))`` with
-    ``b_k ~ U[0.5, 2]``, ``phi_k ~ U[0, 24)``, perturbed per node by the
-    log-normal factor ``exp(0.1 eps - 0.005)``, ``eps ~ N(0, 1)``.
-    Junction demands are set to ``E u_f`` for a per-node flow ``u_f`` sampled
-    in the inner 80 % of the input box, so every node's coupling
-    ``E u + Ed d = 0`` has a solution inside the box.
-    Returns ``(d, u_f)``.
+    Every demand follows ``dhat_k(j) = b_k (1 + 0.3 sin(2 pi (j + phi_k) / 24))``
+    with ``phi_k ~ U[0, 24)``, perturbed per node by the log-normal factor
+    ``exp(0.1 eps - 0.005)``, ``eps ~ N(0, 1)``.  Tank demands use
+    ``b_k ~ U[0.5, 2]``.  Junction demands (consumption at the junction, first
+    ``ne`` entries) use ``b_k`` = 0.25 x the capacity of the junction's inflow,
+    so with the profile and noise they stay below half of it: the point
+    "inflow = junction demand, outflows = 0" satisfies ``E u + Ed d = 0`` inside
+    the input box at every node.
+    Returns ``(d, u_f)`` with ``u_f`` that feasible point per node.
     """
-    M, ne, nd = tree["M"], sys["ne"], sys["nd"]
-    nt = nd - ne
-    b = rng.uniform(0.5, 2.0, nt)
-    phi = rng.uniform(0.0, 24.0, nt)
+    M, ne, nd, nu = tree["M"], sys["ne"], sys["nd"], sys["nu"]
+    E = sys["E"]
+    base = np.empty(nd)
+    base[ne:] = rng.uniform(0.5, 2.0, nd - ne)
+    inflow = np.array([int(np.flatnonzero(E[r] > 0)[0]) for r in range(ne)], dtype=np.int64)
+    base[:ne] = 0.25 * sys["umax"][inflow]
+    phi = rng.uniform(0.0, 24.0, nd)
     hours = (start_hour + tree["stage"]).astype(np.float64)
-    dhat = b[None, :] * (1.0 + 0.3 * np.sin(2.0 * np.pi * (hours[:, None] + phi[None, :]) / 24.0))
-    eps = rng.standard_normal((M, nt))
-    d = np.zeros((M, nd))
-    d[:, ne:] = dhat * np.exp(0.1 * eps - 0.005)
-    span = sys["umax"] - sys["umin"]
-    uf = rng.uniform(sys["umin"] + 0.1 * span, sys["umax"] - 0.1 * span, size=(M, sys["nu"]))
-    d[:, :ne] = uf @ sys["E"].T
+    dhat = base[None, :] * (1.0 + 0.3 * np.sin(2.0 * np.pi * (hours[:, None] + phi[None, :]) / 24.0))
+    eps = rng.standard_normal((M, nd))
+    d = dhat * np.exp(0.1 * eps - 0.005)
+    uf = np.zeros((M, nu))
+    uf[:, inflow] = d[:, :ne]
     return d, uf
 
 
@@ -106,7 +110,7 @@ def barcelona_instance(seed: int = 1, N: int = 24, branching=(7, 7, 7), sys: dic
     d, uf = barcelona_demands(sys, tree, rng)
     alpha2 = pumping_cost(sys, N)
     p = 0.6 * sys["xmax"]
-    q = uf.mean(axis=0)
+    q = 0.3 * sys["umax"]
     return Instance(f"barcelona-N{N}-b{'x'.join(map(str, branching))}", sys, tree, d, alpha2, p, q,
                     extra={"uf": uf})
 
@@ -135,7 +139,7 @@ def batch_instances(n_trees: int = 64, first_seed: int = 100, system_seed: int =
         d, uf = barcelona_demands(sys, tree, rng)
         alpha2 = pumping_cost(sys, N)
         p = sys["xmax"] * rng.uniform(0.4, 0.8, sys["nx"])
-        q = uf.mean(axis=0)
+        q = 0.3 * sys["umax"]
         out.append(Instance(f"batch{seed}-N{N}-s{scen}", sys, tree, d, alpha2, p, q, extra={"uf": uf}))
     return out
 

@@ -59,60 +59,61 @@ N_PUMPS = 38
 
 
 def barcelona_shaped_system(seed: int = 1) -> dict:
-    """A random flow network with the Barcelona DWN dimensions (Sec. V).
+    """A random supplied flow network with the Barcelona DWN dimensions (Sec. V).
 
     63 tanks, 114 flows, 88 demands, 17 junctions, ``A = I``.  Every flow
     carries water from an origin (a source such as a treatment plant or well, a
     tank, or a junction) to a destination (a tank or a junction):
     ``B[dest_tank, j] = +1``, ``B[orig_tank, j] = -1``, and a junction row of
-    ``E`` has +1 for its inflows and -1 for its outflows, so
-    ``E u + Ed d = 0`` with ``Ed = -[I 0]`` is the junction mass balance
-    (first 17 demands).  The flows are: 17 x 3 junction flows (one inflow, from
-    a source for 6 junctions and from a tank for 11, and two outflows to
-    tanks), 14 sources feeding tanks directly and 49 tank-to-tank transfers;
-    every tank receives at least one inflow.  The other 71 demands drain tanks
-    (``Gd = -selector``, every tank drained at least once).
+    ``E`` has +1 for its inflow and -1 for its outflows, so ``E u + Ed d = 0``
+    with ``Ed = -[I 0]`` is the junction mass balance (first 17 demands are
+    junction consumption).  Supply structure: 14 sources feed 14 hub tanks
+    directly and 6 sources feed 6 junctions whose 12 outflows feed 12 more hub
+    tanks; 11 junctions take water from a hub tank and feed 22 tanks; each of
+    the remaining 15 tanks gets a transfer from a hub tank; the remaining 34
+    flows are random tank-to-tank transfers.  Tank and flow labels are then
+    shuffled.  The other 71 demands drain tanks (``Gd = -selector``, every tank
+    drained at least once).
     Tanks ``x in [0, 20 + U(0,30)]`` (soft), safety level ``0.3 x_max``;
-    flows ``u in [0, u_max]``, ``u_max ~ U[4, 12]`` for sources and
-    ``U[2, 10]`` otherwise.  ``alpha1 ~ U[0.5, 2]``; 38 flows are pumps whose
+    flows ``u in [0, u_max]``, ``u_max ~ U[10, 20]`` for sources and
+    ``U[4, 12]`` otherwise.  ``alpha1 ~ U[0.5, 2]``; 38 flows are pumps whose
     time-varying cost weight is stored as ``pump_cols``/``pump_weight``.
     Weights keep the paper's ratios (``W_u = 5 I, W_x = 500, gamma_d = 2500``).
     """
     rng = np.random.default_rng(seed)
     nx, nu, nd, ne = 63, 114, 88, 17
-    # (origin kind, destination kind): kinds are "src", "tank", "junc"
-    flows = []
-    for r in range(ne):
-        flows.append(("src" if r < 6 else "tank", ("junc", r)))
-        flows.append((("junc", r), "tank"))
-        flows.append((("junc", r), "tank"))
-    flows += [("src", "tank")] * 14
-    flows += [("tank", "tank")] * (nu - len(flows))
-    assert len(flows) == nu
+    flows = []  # (origin, destination): ("src",), ("tank", k), ("junc", r)
+    hubs = list(range(26))
+    for k in range(14):
+        flows.append((("src",), ("tank", k)))
+    for r in range(6):
+        flows.append((("src",), ("junc", r)))
+        flows.append((("junc", r), ("tank", 14 + 2 * r)))
+        flows.append((("junc", r), ("tank", 15 + 2 * r)))
+    for r in range(6, ne):
+        flows.append((("tank", int(rng.choice(hubs))), ("junc", r)))
+        flows.append((("junc", r), ("tank", 26 + 2 * (r - 6))))
+        flows.append((("junc", r), ("tank", 27 + 2 * (r - 6))))
+    for k in range(48, nx):
+        flows.append((("tank", int(rng.choice(hubs))), ("tank", k)))
+    while len(flows) < nu:
+        a, b = rng.choice(nx, size=2, replace=False)
+        flows.append((("tank", int(a)), ("tank", int(b))))
+    tank_label = rng.permutation(nx)
     order = rng.permutation(nu)
     flows = [flows[k] for k in order]
-    n_dest_tank = sum(1 for f in flows if f[1] == "tank")
-    dest_tanks = np.concatenate([rng.permutation(nx), rng.integers(0, nx, size=n_dest_tank - nx)])
-    rng.shuffle(dest_tanks)
     B = np.zeros((nx, nu))
     E = np.zeros((ne, nu))
     is_src = np.zeros(nu, dtype=bool)
-    k = 0
     for j, (orig, dest) in enumerate(flows):
-        if dest == "tank":
-            dt = int(dest_tanks[k])
-            k += 1
-            B[dt, j] = 1.0
+        if dest[0] == "tank":
+            B[tank_label[dest[1]], j] = 1.0
         else:
-            dt = -1
             E[dest[1], j] = 1.0
-        if orig == "src":
+        if orig[0] == "src":
             is_src[j] = True
-        elif orig == "tank":
-            ot = int(rng.integers(0, nx))
-            while ot == dt:
-                ot = int(rng.integers(0, nx))
-            B[ot, j] = -1.0
+        elif orig[0] == "tank":
+            B[tank_label[orig[1]], j] = -1.0
         else:
             E[orig[1], j] = -1.0
     assert np.linalg.matrix_rank(E) == ne
@@ -123,7 +124,7 @@ def barcelona_shaped_system(seed: int = 1) -> dict:
     tanks = np.concatenate([rng.permutation(nx), rng.integers(0, nx, size=len(tank_cols) - nx)])
     Gd[tanks, tank_cols] = -1.0
     xmax = 20.0 + rng.uniform(0.0, 30.0, nx)
-    umax = np.where(is_src, rng.uniform(4.0, 12.0, nu), rng.uniform(2.0, 10.0, nu))
+    umax = np.where(is_src, rng.uniform(10.0, 20.0, nu), rng.uniform(4.0, 12.0, nu))
     pump_cols = np.sort(rng.choice(nu, size=N_PUMPS, replace=False))
     pump_weight = rng.uniform(0.0, 1.0, N_PUMPS)
     return {
