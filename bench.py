@@ -88,6 +88,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=20000)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and has no multi-GPU path "
@@ -106,7 +107,7 @@ def main() -> int:
     system, tree = solver.from_instance(ctx, inst, precond=1, power_iters=200)
     lam, S = tree.factor_info(with_scale=True)
     info = tree.info()
-    opts = dict(tol=1e-3, max_iter=20000, check_every=10, precision=64, want_x=False, want_y=False)
+    opts = dict(tol=1e-3, max_iter=a.max_iter, check_every=10, precision=64, want_x=False, want_y=False)
     print(f"[bench] plain FP64: M={inst.M} chains={info['n_chains']} levels={info['n_levels']} lambda={lam:.4e}",
           file=sys.stderr, flush=True)
     for _ in range(a.warmup):
@@ -119,6 +120,7 @@ def main() -> int:
         r = tree.solve(inst.p, inst.q, **opts)
         lat.append(time.perf_counter() - s0)
         iters.append(r["iterations"])
+        print(f"[bench] step {len(iters)}: {r['iterations']} it in {lat[-1]:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = sum(iters) / elapsed
@@ -128,8 +130,9 @@ def main() -> int:
     # same steps again with per-kernel HIP events for the roofline
     ctx.reset_stats()
     ctx.profiling(True)
-    for _ in range(a.steps):
+    for k in range(a.steps):
         tree.solve(inst.p, inst.q, **opts)
+        print(f"[bench] profiled step {k + 1}", file=sys.stderr, flush=True)
     stats = ctx.kernel_stats()
     ctx.profiling(False)
     dom = max(stats, key=lambda k: stats[k]["total_ms"])

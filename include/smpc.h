@@ -96,8 +96,7 @@ typedef struct {
 /* Copies the system, checks it (SMPC_ENAN, SMPC_EDIM, SMPC_EINVAL for
  * umin > umax or xmin > xmax, SMPC_ENOTSPD for Wu, SMPC_ERANK for E) and runs
  * the tree-independent part of the factor step (App. A / App. B) in float64
- * on the host.  Supported: 1 <= nx, 1 <= nu <= 136, 0 <= ne < nu,
- * 2*nx + nu <= 1024.                                                         */
+ * on the host.  Supported: 1 <= nx <= 128, 1 <= nu <= 128, 0 <= ne < nu.   */
 int smpc_sys_create(smpc_ctx* ctx, const smpc_sys_desc* desc, smpc_sys** out);
 int smpc_sys_destroy(smpc_sys* sys);   /* SMPC_EINVAL while trees still use it */
 

@@ -100,6 +100,7 @@ int smpc_ctx::ensure_ctab(int n) {
   used += sizeof(double) * len;
   HIP_TRY(hipMemcpy(ctab, h.data(), sizeof(double) * len, hipMemcpyHostToDevice));
   ctab_len = len;
+  ++ctab_gen;
   return SMPC_OK;
 }
 
@@ -172,7 +173,13 @@ int upload_i32(smpc_ctx* ctx, DevBuf& b, const std::vector<int32_t>& v) {
 template <typename T>
 int sys_upload(smpc_sys* s, SysBuffers<T>& d) {
   smpc_ctx* ctx = s->ctx;
-  SMPC_TRY(upload<T>(ctx, d.P, s->P.data(), s->P.size()));
+  {
+    const int kp = p_stride(s->nu);
+    std::vector<double> pp((size_t)kp * kp, 0.0);
+    for (int i = 0; i < s->nu; ++i)
+      for (int j = 0; j < s->nu; ++j) pp[(size_t)i * kp + j] = s->P[(size_t)i * s->nu + j];
+    SMPC_TRY(upload<T>(ctx, d.P, pp.data(), pp.size()));
+  }
   SMPC_TRY(upload_i32(ctx, d.b_rp, s->Bc.rp));
   SMPC_TRY(upload_i32(ctx, d.b_ci, s->Bc.ci));
   SMPC_TRY(upload<T>(ctx, d.b_v, s->Bc.v.data(), s->Bc.v.size()));
@@ -321,8 +328,15 @@ int tree_upload_scale(smpc_tree* t) {
   return upload<T>(t->sys->ctx, b.scale, t->scale.data(), t->scale.size());
 }
 
+void plan_drop_graphs(Plan* p) {
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+}
+
 void plan_free(smpc_ctx* ctx, Plan* p) {
   if (!p) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  plan_drop_graphs(p);
   ctx->release(p->items);
   ctx->release(p->td64);
   ctx->release(p->td32);
@@ -441,11 +455,48 @@ int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, bool with
   return SMPC_OK;
 }
 
+// Enqueue `iters` iterations.  Without profiling they are captured once into a
+// hipGraph per (precision, mode, iters) and replayed: the kernels take every
+// per-iteration quantity from the device-side tree state, so one graph serves
+// every block of a solve.
+template <typename T>
+int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
+  if (ctx->profiling) {
+    for (int k = 0; k < iters; ++k) SMPC_TRY(enqueue_iteration<T>(ctx, sys, p, mode, true));
+    return SMPC_OK;
+  }
+  if (p->graphs_ctab_gen != ctx->ctab_gen) {
+    plan_drop_graphs(p);
+    p->graphs_ctab_gen = ctx->ctab_gen;
+  }
+  const auto key = std::make_tuple((int)sizeof(T), mode, iters);
+  auto found = p->graphs.find(key);
+  if (found == p->graphs.end()) {
+    HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    int rc = SMPC_OK;
+    for (int k = 0; k < iters && rc >= 0; ++k) rc = enqueue_iteration<T>(ctx, sys, p, mode, true);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+    if (rc < 0) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return set_error(SMPC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return set_error(SMPC_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    found = p->graphs.emplace(key, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(found->second, ctx->stream));
+  return SMPC_OK;
+}
+
 // Run APG iterations until every tree of the plan is done.
 template <typename T>
 int run_until_done(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int check_every, int max_rounds) {
   for (int round = 0; round < max_rounds; ++round) {
-    for (int k = 0; k < check_every; ++k) SMPC_TRY(enqueue_iteration<T>(ctx, sys, p, kModeAPG, true));
+    SMPC_TRY(run_block<T>(ctx, sys, p, kModeAPG, check_every));
     HIP_TRY(hipMemcpyAsync(p->done_host.data(), p->done.ptr, sizeof(int32_t) * p->trees.size(),
                            hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -790,9 +841,9 @@ int smpc_sys_create(smpc_ctx* ctx, const smpc_sys_desc* d, smpc_sys** out) {
   *out = nullptr;
   const int nx = d->nx, nu = d->nu, nd = d->nd, ne = d->ne;
   if (nx < 1 || nu < 1 || nd < 0 || ne < 0) return set_error(SMPC_EDIM, "dimensions must be positive");
-  if (nu > 136) return set_error(SMPC_EDIM, "nu = %d exceeds the supported 136", nu);
+  if (nu > 128) return set_error(SMPC_EDIM, "nu = %d exceeds the supported 128", nu);
+  if (nx > 128) return set_error(SMPC_EDIM, "nx = %d exceeds the supported 128", nx);
   if (ne >= nu) return set_error(SMPC_EDIM, "ne = %d must be < nu = %d", ne, nu);
-  if (2 * nx + nu > 4 * kBlock) return set_error(SMPC_EDIM, "2 nx + nu = %d exceeds %d", 2 * nx + nu, 4 * kBlock);
   if (!d->A || !d->B || (nd > 0 && !d->Gd) || !d->umin || !d->umax || !d->xmin || !d->xmax || !d->xs ||
       !d->alpha1 || !d->Wu)
     return set_error(SMPC_EINVAL, "missing system matrix");
@@ -844,10 +895,6 @@ int smpc_sys_create(smpc_ctx* ctx, const smpc_sys_desc* d, smpc_sys** out) {
   if (rc < 0) {
     delete s;
     return rc;
-  }
-  if (lds_bytes_backward(nx, nu, sizeof(double)) > 160 * 1024) {
-    delete s;
-    return set_error(SMPC_EDIM, "system too large for the LDS-resident factor");
   }
   rc = sys_upload<double>(s, s->d64);
   if (rc < 0) {
@@ -1103,7 +1150,7 @@ int smpc_factor(smpc_tree* t, const smpc_factor_opts* o) {
   st.in_scale = 1.0 / std::sqrt(nrm);
   SMPC_TRY(write_state(t, st));
   const int iters = o->power_iters > 0 ? o->power_iters : 200;
-  for (int k = 0; k < iters; ++k) SMPC_TRY(enqueue_iteration<double>(ctx, s, t->plan, kModePower, true));
+  for (int k = 0; k < iters; k += 10) SMPC_TRY(run_block<double>(ctx, s, t->plan, kModePower, std::min(10, iters - k)));
   SMPC_TRY(read_state(t, &st));
   if (!(st.lmax_est > 0.0) || !std::isfinite(st.lmax_est))
     return set_error(SMPC_EDEVICE, "power iteration failed (estimate %g)", st.lmax_est);

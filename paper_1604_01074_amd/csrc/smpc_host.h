@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -58,6 +59,7 @@ struct smpc_ctx {
   std::vector<smpc::ProfRec> prof;
   std::vector<hipEvent_t> ev_pool;
   std::map<std::string, std::pair<int, double>> stats;
+  int ctab_gen = 0;  // bumped whenever ctab is reallocated (captured graphs hold its address)
   // cached batch launch plan
   struct Plan* batch_plan = nullptr;
 
@@ -133,6 +135,9 @@ struct Plan {
   smpc::DevBuf items, td64, td32, refs, done;
   std::vector<int32_t> done_host;
   bool has32 = false;
+  // instantiated graphs of `iters` iterations, keyed by (element size, mode, iters)
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+  int graphs_ctab_gen = -1;
 };
 
 namespace smpc {

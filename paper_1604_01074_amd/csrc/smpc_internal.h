@@ -79,7 +79,7 @@ template <typename T>
 struct SysDev {
   int32_t nx, nu, D;
   int32_t a_identity;
-  const T* P;                                          // nu x nu, symmetric
+  const T* P;            // p_stride(nu) x p_stride(nu), symmetric, zero-padded
   const int32_t* b_rp; const int32_t* b_ci; const T* b_v;     // B  (CSR)
   const int32_t* bt_rp; const int32_t* bt_ci; const T* bt_v;  // B' (CSR)
   const int32_t* a_rp; const int32_t* a_ci; const T* a_v;     // A  (CSR)
@@ -130,6 +130,8 @@ hipError_t launch_convert_dual(const double* src, T* dst, size_t n, hipStream_t 
 template <typename T>
 hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s);
 
+// Row stride of the zero-padded P on the device (and of the staged rho rows).
+int p_stride(int nu);
 size_t lds_bytes_backward(int nx, int nu, size_t elem);
 size_t lds_bytes_forward(int nx, int nu, size_t elem);
 

@@ -43,7 +43,7 @@ def test_system_validation(S, ctx):
     E = r["E"].copy()
     E[1] = E[0]
     assert _code(S, S.smpc_sys_create, ctx, dict(r, E=E)) == S.ERANK
-    big = ds.random_dense_system(0, nx=3, nu=140, nd=2, ne=1)
+    big = ds.random_dense_system(0, nx=3, nu=130, nd=2, ne=1)
     assert _code(S, S.smpc_sys_create, ctx, big) == S.EDIM
 
 

@@ -247,3 +247,25 @@ def test_torch_stream_interop(ctx, lib):
         system.close()
         ctx.systems.remove(system)
     assert np.array_equal(r1["y"], r2["y"]) and np.array_equal(r1["u"], r2["u"])
+
+
+def test_graph_replay_equals_eager_launches(ctx, lib):
+    """Solves replay captured iteration blocks (hipGraph); with profiling on
+    the same iterations are launched one by one.  Both give the same bits,
+    over many replays with host synchronisation between them."""
+    _, solver = lib
+    inst = ds.barcelona_instance(N=8, branching=(3, 2))
+    system, tree = solver.from_instance(ctx, inst, precond=1, power_iters=50)
+    try:
+        for precision, polish in ((64, 0), (32, 5)):
+            kw = dict(tol=0.0, max_iter=120, check_every=10, precision=precision, polish_iters=polish)
+            g1 = tree.solve(inst.p, inst.q, **kw)
+            ctx.profiling(True)
+            e1 = tree.solve(inst.p, inst.q, **kw)
+            ctx.profiling(False)
+            g2 = tree.solve(inst.p, inst.q, **kw)
+            for k in ("y", "u", "x"):
+                assert np.array_equal(g1[k], e1[k]) and np.array_equal(g1[k], g2[k])
+    finally:
+        system.close()
+        ctx.systems.remove(system)
