@@ -89,6 +89,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--only-batch", action="store_true", help="run only the batched FP32 leg (profiling aid)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device a few times (scales HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and has no multi-GPU path "
@@ -101,6 +104,21 @@ def main() -> int:
     from paper_1604_01074_amd import solver
 
     torch.cuda.set_device(0)
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                          "launches": 5}), flush=True)
+        return 0
+    if a.only_batch:
+        ctx = solver.Context(0)
+        print(json.dumps({"batched_fp32": batched_leg(ctx, a.batch_steps, a.max_iter)}), flush=True)
+        ctx.close()
+        return 0
     inst = ds.barcelona_instance()
     nx, nu = inst.sys["nx"], inst.sys["nu"]
     ctx = solver.Context(0)
@@ -113,13 +131,14 @@ def main() -> int:
     for _ in range(a.warmup):
         tree.solve(inst.p, inst.q, **opts)
     torch.cuda.synchronize()
-    lat, iters = [], []
+    lat, iters, conv = [], [], []
     t0 = time.perf_counter()
     for _ in range(a.steps):
         s0 = time.perf_counter()
         r = tree.solve(inst.p, inst.q, **opts)
         lat.append(time.perf_counter() - s0)
         iters.append(r["iterations"])
+        conv.append(r["status"] == 0)
         print(f"[bench] step {len(iters)}: {r['iterations']} it in {lat[-1]:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -137,9 +156,8 @@ def main() -> int:
     ctx.profiling(False)
     dom = max(stats, key=lambda k: stats[k]["total_ms"])
     avg_ms = stats[dom]["total_ms"] / stats[dom]["launches"]
-    # nodes one launch of the dominant kernel covers
-    leaf = dom.split("_")[1] == "leaf"
-    nodes_per_launch = _level_nodes(inst.tree, leaf)
+    # one launch of either kernel covers every node of the tree once
+    nodes_per_launch = inst.M
     per_node = node_bytes(dom, nx, nu, 8, True)
     achieved = per_node * nodes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -166,6 +184,8 @@ def main() -> int:
                                "branching [7,7,7] (343 scenarios, 7260 nodes), tol 1e-3, cold start",
                    "nodes": inst.M, "tol": 1e-3, "check_every": 10, "precond": "single-branch diagonal"},
         "solves_per_s": round(a.steps / elapsed, 3),
+        "solves_reaching_tol": int(sum(conv)),
+        "r_primal_at_exit": r["r_primal"],
         "iterations_per_solve": iters[0],
         "node_iterations_per_s": round(value * inst.M, 1),
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
@@ -177,7 +197,7 @@ def main() -> int:
     }
 
     if not a.no_batch:
-        out["batched_fp32"] = batched_leg(ctx, a.batch_steps)
+        out["batched_fp32"] = batched_leg(ctx, a.batch_steps, a.max_iter)
 
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds, S, lam)
@@ -186,24 +206,7 @@ def main() -> int:
     return 0
 
 
-def _level_nodes(tree: dict, leaf: bool) -> int:
-    """Nodes covered by the leaf-chain (after the last branching) or the
-    inner levels of a tree."""
-    par = np.asarray(tree["parent"])
-    M = tree["M"]
-    nch = np.bincount(par[par >= 0], minlength=M)
-    # a node belongs to a leaf chain when no node on its path below branches
-    below_branch = np.zeros(M, dtype=bool)
-    for n in range(M - 1, -1, -1):
-        if nch[n] >= 2:
-            below_branch[n] = True
-        if par[n] >= 0 and below_branch[n]:
-            below_branch[par[n]] = True
-    leaf_nodes = int((~below_branch).sum())
-    return leaf_nodes if leaf else M - leaf_nodes
-
-
-def batched_leg(ctx, steps: int) -> dict:
+def batched_leg(ctx, steps: int, max_iter: int) -> dict:
     import torch
 
     import dwn_synth as ds
@@ -212,21 +215,25 @@ def batched_leg(ctx, steps: int) -> dict:
     system = ctx.system(insts[0].sys)
     trees = []
     t0 = time.perf_counter()
-    for inst in insts:
+    for k, inst in enumerate(insts):
         t = system.tree(inst.tree)
         t.set_data(inst.d, inst.alpha2)
         t.factor(precond=1, power_iters=100)
         trees.append(t)
+        if k % 16 == 15:
+            print(f"[bench] batch setup {k + 1}/{len(insts)}", file=sys.stderr, flush=True)
     setup_s = time.perf_counter() - t0
     nodes = sum(i.M for i in insts)
-    kw = dict(tol=1e-3, max_iter=20000, check_every=10, precision=32, polish_iters=20, want_x=False, want_y=False)
+    kw = dict(tol=1e-3, max_iter=max_iter, check_every=10, precision=32, polish_iters=20, want_x=False, want_y=False)
     ps = [i.p for i in insts]
     qs = [i.q for i in insts]
+    print(f"[bench] batch: {len(trees)} trees, {nodes} nodes, setup {setup_s:.1f} s", file=sys.stderr, flush=True)
     system.solve_batch(trees, ps, qs, **kw)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         code, res = system.solve_batch(trees, ps, qs, **kw)
+        print(f"[bench] batch step {k + 1}: {time.perf_counter() - t0:.2f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tree_iters = sum(r["iterations"] for r in res) * steps
@@ -236,6 +243,7 @@ def batched_leg(ctx, steps: int) -> dict:
            "node_iterations_per_s": round(node_iters / dt, 1),
            "ms_per_batch": round(1e3 * dt / steps, 2),
            "iterations_max": max(r["iterations"] for r in res),
+           "trees_reaching_tol": int(sum(1 for r in res if r["status"] == 0)),
            "iterations_median": float(np.median([r["iterations"] for r in res])),
            "fp32_iterations_median": float(np.median([r["fp32_iterations"] for r in res])),
            "status_worst": int(code), "setup_s": round(setup_s, 2), "dtype": "f32 bulk + 20 f64 polish"}

@@ -272,8 +272,6 @@ int tree_alloc(smpc_tree* t) {
     SMPC_TRY(ctx->alloc(b.z, sizeof(T) * M * (nx + nu)));
     SMPC_TRY(ctx->alloc(b.ctopQ, sizeof(T) * C * nx));
     SMPC_TRY(ctx->alloc(b.ctopR, sizeof(T) * C * nu));
-    SMPC_TRY(ctx->alloc(b.cbotX, sizeof(T) * C * nx));
-    SMPC_TRY(ctx->alloc(b.cbotU, sizeof(T) * C * nu));
     for (int k = 0; k < 3; ++k) HIP_TRY(hipMemsetAsync(b.y[k].ptr, 0, sizeof(T) * M * D, ctx->stream));
     b.allocated = true;
     std::vector<double> pii(M);
@@ -292,8 +290,11 @@ int tree_alloc(smpc_tree* t) {
   v.z = (T*)b.z.ptr;
   v.ctopQ = (T*)b.ctopQ.ptr;
   v.ctopR = (T*)b.ctopR.ptr;
-  v.cbotX = (T*)b.cbotX.ptr;
-  v.cbotU = (T*)b.cbotU.ptr;
+  v.cnt = (int32_t*)t->cnt.ptr;
+  v.leaves = (const int32_t*)t->leaves_dev.ptr;
+  v.path_off = (const int32_t*)t->path_off_dev.ptr;
+  v.path = (const int32_t*)t->path_dev.ptr;
+  v.n_leaves = (int32_t)t->leaves.size();
   v.cstat = (double*)t->cstat.ptr;
   v.chains = (const ChainDesc*)t->chains_dev.ptr;
   v.st = (TreeState*)t->st.ptr;
@@ -305,7 +306,7 @@ int tree_alloc(smpc_tree* t) {
 template <typename T>
 void tree_free(smpc_ctx* ctx, TreeBuffers<T>& b) {
   DevBuf* all[] = {&b.y[0], &b.y[1], &b.y[2], &b.beta, &b.uhat, &b.e, &b.pi, &b.scale, &b.p,
-                   &b.du, &b.z, &b.ctopQ, &b.ctopR, &b.cbotX, &b.cbotU};
+                   &b.du, &b.z, &b.ctopQ, &b.ctopR};
   for (DevBuf* d : all) ctx->release(*d);
   b.allocated = false;
 }
@@ -340,62 +341,43 @@ void plan_free(smpc_ctx* ctx, Plan* p) {
   ctx->release(p->items);
   ctx->release(p->td64);
   ctx->release(p->td32);
-  ctx->release(p->refs);
   ctx->release(p->done);
   delete p;
 }
 
-// Build the launch plan of a set of trees: for every chain height, the work
-// items of all trees (longest chains first), and the device tree tables.
+// Build the launch plan of a set of trees: the leaf chains of all trees
+// (longest first) and the device tree tables.
 int plan_build(smpc_ctx* ctx, const std::vector<smpc_tree*>& trees, bool need32, Plan** out) {
   Plan* p = new (std::nothrow) Plan();
   if (!p) return set_error(SMPC_ENOMEM, "host allocation failed");
   p->trees = trees;
-  int H = 0;
-  for (auto* t : trees) H = std::max(H, t->n_levels);
-  p->H = H;
-  std::vector<WorkItem> items;
-  for (int h = 0; h < H; ++h) {
-    p->lvl_off.push_back((int)items.size());
-    std::vector<std::pair<int, WorkItem>> lvl;
-    for (size_t k = 0; k < trees.size(); ++k) {
-      const smpc_tree* t = trees[k];
-      if (h >= t->n_levels) continue;
-      for (int32_t c : t->level_chains[h]) lvl.push_back({t->chains[c].len, WorkItem{(int32_t)k, c}});
-    }
-    std::stable_sort(lvl.begin(), lvl.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-    for (auto& w : lvl) items.push_back(w.second);
-    p->lvl_cnt.push_back((int)items.size() - p->lvl_off.back());
+  std::vector<std::pair<int, WorkItem>> lv;
+  for (size_t k = 0; k < trees.size(); ++k) {
+    const smpc_tree* t = trees[k];
+    for (int32_t c : t->leaves) lv.push_back({t->chains[c].len, WorkItem{(int32_t)k, c}});
   }
+  std::stable_sort(lv.begin(), lv.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<WorkItem> items;
+  for (auto& w : lv) items.push_back(w.second);
+  p->n_items = (int)items.size();
   int rc = ctx->alloc(p->items, sizeof(WorkItem) * std::max<size_t>(items.size(), 1));
+  if (rc >= 0) rc = ctx->alloc(p->done, sizeof(int32_t) * trees.size());
   if (rc < 0) { plan_free(ctx, p); return rc; }
   std::vector<TreeDev<double>> t64;
   std::vector<TreeDev<float>> t32;
-  std::vector<IterRef> refs;
-  rc = ctx->alloc(p->done, sizeof(int32_t) * trees.size());
-  if (rc < 0) { plan_free(ctx, p); return rc; }
-  for (size_t k = 0; k < trees.size(); ++k) {
-    smpc_tree* t = trees[k];
+  for (smpc_tree* t : trees) {
     t64.push_back(t->b64.view);
     if (need32) t32.push_back(t->b32.view);
-    IterRef r{};
-    r.st = (TreeState*)t->st.ptr;
-    r.cstat = (const double*)t->cstat.ptr;
-    r.done_out = (int32_t*)p->done.ptr;
-    r.n_chains = (int32_t)t->chains.size();
-    r.slot = (int32_t)k;
-    refs.push_back(r);
   }
   rc = ctx->alloc(p->td64, sizeof(TreeDev<double>) * t64.size());
   if (rc >= 0 && need32) rc = ctx->alloc(p->td32, sizeof(TreeDev<float>) * t32.size());
-  if (rc >= 0) rc = ctx->alloc(p->refs, sizeof(IterRef) * refs.size());
   if (rc < 0) { plan_free(ctx, p); return rc; }
   hipStream_t s = ctx->stream;
   hipError_t e = hipSuccess;
   if (!items.empty()) e = hipMemcpyAsync(p->items.ptr, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(p->td64.ptr, t64.data(), sizeof(TreeDev<double>) * t64.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && need32) e = hipMemcpyAsync(p->td32.ptr, t32.data(), sizeof(TreeDev<float>) * t32.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(p->refs.ptr, refs.data(), sizeof(IterRef) * refs.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(p->done.ptr, 0, sizeof(int32_t) * trees.size(), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     plan_free(ctx, p);
@@ -415,43 +397,29 @@ template <>
 const TreeDev<float>* plan_td<float>(Plan* p) { return (const TreeDev<float>*)p->td32.ptr; }
 
 template <typename T>
-const char* kname(int which, int h);
+const char* kname(int which);
 template <>
-const char* kname<double>(int which, int h) {
-  static const char* n[3][2] = {{"backward_leaf_f64", "backward_inner_f64"},
-                                {"forward_leaf_f64", "forward_inner_f64"},
-                                {"iter_end", "iter_end"}};
-  return n[which][h == 0 ? 0 : 1];
+const char* kname<double>(int which) {
+  return which == 0 ? "backward_f64" : "forward_f64";
 }
 template <>
-const char* kname<float>(int which, int h) {
-  static const char* n[3][2] = {{"backward_leaf_f32", "backward_inner_f32"},
-                                {"forward_leaf_f32", "forward_inner_f32"},
-                                {"iter_end", "iter_end"}};
-  return n[which][h == 0 ? 0 : 1];
+const char* kname<float>(int which) {
+  return which == 0 ? "backward_f32" : "forward_f32";
 }
 
-// Enqueue one iteration (all levels backward, all levels forward, then the
-// per-tree bookkeeping) of `mode` for every tree of the plan.
+// Enqueue one iteration of `mode` for every tree of the plan: the backward
+// sweep over all chains, then the forward rollout with prox and the per-tree
+// end of iteration.
 template <typename T>
-int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, bool with_end) {
+int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode) {
   const SysDev<T>& sv = sysbuf<T>(sys).view;
   const TreeDev<T>* td = plan_td<T>(p);
   const WorkItem* items = (const WorkItem*)p->items.ptr;
   hipStream_t s = ctx->stream;
-  for (int h = 0; h < p->H; ++h) {
-    HIP_TRY(timed(ctx, kname<T>(0, h), [&] {
-      return launch_backward<T>(sv, td, items + p->lvl_off[h], p->lvl_cnt[h], ctx->ctab, mode, s);
-    }));
-  }
-  for (int h = p->H - 1; h >= 0; --h) {
-    HIP_TRY(timed(ctx, kname<T>(1, h), [&] {
-      return launch_forward<T>(sv, td, items + p->lvl_off[h], p->lvl_cnt[h], ctx->ctab, mode, s);
-    }));
-  }
-  if (with_end) {
-    HIP_TRY(timed(ctx, "iter_end", [&] { return launch_iter_end_refs(p->refs.ptr, (int)p->trees.size(), mode, s); }));
-  }
+  HIP_TRY(timed(ctx, kname<T>(0), [&] { return launch_backward<T>(sv, td, items, p->n_items, ctx->ctab, mode, s); }));
+  HIP_TRY(timed(ctx, kname<T>(1), [&] {
+    return launch_forward<T>(sv, td, items, p->n_items, ctx->ctab, mode, (int32_t*)p->done.ptr, s);
+  }));
   return SMPC_OK;
 }
 
@@ -462,7 +430,7 @@ int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, bool with
 template <typename T>
 int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
   if (ctx->profiling) {
-    for (int k = 0; k < iters; ++k) SMPC_TRY(enqueue_iteration<T>(ctx, sys, p, mode, true));
+    for (int k = 0; k < iters; ++k) SMPC_TRY(enqueue_iteration<T>(ctx, sys, p, mode));
     return SMPC_OK;
   }
   if (p->graphs_ctab_gen != ctx->ctab_gen) {
@@ -474,7 +442,7 @@ int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
   if (found == p->graphs.end()) {
     HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     int rc = SMPC_OK;
-    for (int k = 0; k < iters && rc >= 0; ++k) rc = enqueue_iteration<T>(ctx, sys, p, mode, true);
+    for (int k = 0; k < iters && rc >= 0; ++k) rc = enqueue_iteration<T>(ctx, sys, p, mode);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
     if (rc < 0) {
@@ -1003,29 +971,51 @@ int smpc_tree_create(smpc_sys* sys, int N, int M, const int32_t* stage, const in
     H = std::max(H, h + 1);
   }
   t->n_levels = H;
-  t->level_chains.assign(H, {});
-  for (int c = 0; c < (int)t->chains.size(); ++c) t->level_chains[t->chains[c].height].push_back(c);
-  for (auto& l : t->level_chains)
-    std::stable_sort(l.begin(), l.end(), [&](int a, int b) { return t->chains[a].len > t->chains[b].len; });
+  // leaf chains; each inner chain is owned (its prox is done) by its first
+  // leaf descendant; the root path of every leaf chain, root first
+  const int C0 = (int)t->chains.size();
+  std::vector<int> first_leaf(C0, -1);
+  for (int c = C0 - 1; c >= 0; --c) {
+    const ChainDesc& cd = t->chains[c];
+    first_leaf[c] = cd.child_count == 0 ? c : first_leaf[cd.child_begin];
+    if (cd.child_count == 0) t->leaves.push_back(c);
+  }
+  std::reverse(t->leaves.begin(), t->leaves.end());
+  t->path_off.assign(C0 + 1, 0);
+  t->path.clear();
+  for (int c = 0; c < C0; ++c) {
+    t->path_off[c] = (int32_t)t->path.size();
+    if (t->chains[c].child_count == 0) {
+      std::vector<int32_t> anc;
+      for (int a = t->chains[c].parent; a >= 0; a = t->chains[a].parent) anc.push_back(a);
+      for (auto it = anc.rbegin(); it != anc.rend(); ++it)
+        t->path.push_back(first_leaf[*it] == c ? -1 - *it : *it);
+    }
+  }
+  t->path_off[C0] = (int32_t)t->path.size();
   // device state
   smpc_ctx* ctx = sys->ctx;
   const size_t C = t->chains.size();
   int rc = ctx->alloc(t->cstat, sizeof(double) * kStat * C);
   if (rc >= 0) rc = ctx->alloc(t->st, sizeof(TreeState));
   if (rc >= 0) rc = ctx->alloc(t->chains_dev, sizeof(ChainDesc) * C);
+  if (rc >= 0) rc = ctx->alloc(t->cnt, sizeof(int32_t) * C);
+  if (rc >= 0) rc = upload_i32(ctx, t->leaves_dev, t->leaves);
+  if (rc >= 0) rc = upload_i32(ctx, t->path_off_dev, t->path_off);
+  if (rc >= 0) rc = upload_i32(ctx, t->path_dev, t->path);
   if (rc >= 0) {
     hipError_t e = hipMemcpyAsync(t->chains_dev.ptr, t->chains.data(), sizeof(ChainDesc) * C, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(t->cstat.ptr, 0, sizeof(double) * kStat * C, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(t->st.ptr, 0, sizeof(TreeState), ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(t->cnt.ptr, 0, sizeof(int32_t) * C, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) rc = set_error(SMPC_EDEVICE, "tree upload failed: %s", hipGetErrorString(e));
   }
   if (rc >= 0) rc = tree_alloc<double>(t);
   if (rc < 0) {
     tree_free(ctx, t->b64);
-    ctx->release(t->cstat);
-    ctx->release(t->st);
-    ctx->release(t->chains_dev);
+    DevBuf* extra[] = {&t->cstat, &t->st, &t->chains_dev, &t->cnt, &t->leaves_dev, &t->path_off_dev, &t->path_dev};
+    for (DevBuf* b : extra) ctx->release(*b);
     delete t;
     return rc;
   }
@@ -1045,9 +1035,8 @@ int smpc_tree_destroy(smpc_tree* t) {
   if (t->plan) plan_free(ctx, t->plan);
   tree_free(ctx, t->b64);
   tree_free(ctx, t->b32);
-  ctx->release(t->cstat);
-  ctx->release(t->st);
-  ctx->release(t->chains_dev);
+  DevBuf* extra[] = {&t->cstat, &t->st, &t->chains_dev, &t->cnt, &t->leaves_dev, &t->path_off_dev, &t->path_dev};
+  for (DevBuf* b : extra) ctx->release(*b);
   t->sys->n_trees--;
   delete t;
   return SMPC_OK;
@@ -1268,13 +1257,13 @@ int smpc_solve_step(smpc_tree* t, const double* p, const double* q, const double
   if (use32) {
     SMPC_TRY(upload_root<float>(t, p, q));
     SMPC_TRY(put(float{}));
-    SMPC_TRY(enqueue_iteration<float>(ctx, s, t->plan, kModeSolve, false));
+    SMPC_TRY(enqueue_iteration<float>(ctx, s, t->plan, kModeSolve));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     SMPC_TRY(download_primal<float>(t, x, u, nullptr));
   } else {
     SMPC_TRY(upload_root<double>(t, p, q));
     SMPC_TRY(put(double{}));
-    SMPC_TRY(enqueue_iteration<double>(ctx, s, t->plan, kModeSolve, false));
+    SMPC_TRY(enqueue_iteration<double>(ctx, s, t->plan, kModeSolve));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     SMPC_TRY(download_primal<double>(t, x, u, nullptr));
   }

@@ -96,7 +96,7 @@ struct smpc_sys {
 
 template <typename T>
 struct TreeBuffers {
-  smpc::DevBuf y[3], beta, uhat, e, pi, scale, p, du, z, ctopQ, ctopR, cbotX, cbotU;
+  smpc::DevBuf y[3], beta, uhat, e, pi, scale, p, du, z, ctopQ, ctopR;
   smpc::TreeDev<T> view{};
   bool allocated = false;
 };
@@ -111,7 +111,9 @@ struct smpc_tree {
   std::vector<int32_t> iperm;  // caller -> internal index
   std::vector<smpc::ChainDesc> chains;
   int n_levels = 0;
-  std::vector<std::vector<int32_t>> level_chains;  // chains of each height, longest first
+  std::vector<int32_t> leaves;    // chains that end at a leaf
+  std::vector<int32_t> path_off;  // per chain: range in `path`
+  std::vector<int32_t> path;      // ancestors of each leaf chain (root first); -1-id = owned
   // float64 host copies of the per-node data, internal order
   std::vector<double> beta0;  // beta with q = 0 (root term added per solve)
   std::vector<double> uhat, e, pi;
@@ -123,16 +125,15 @@ struct smpc_tree {
   // device
   TreeBuffers<double> b64;
   TreeBuffers<float> b32;
-  smpc::DevBuf cstat, st, chains_dev;
+  smpc::DevBuf cstat, st, chains_dev, cnt, leaves_dev, path_off_dev, path_dev;
   struct Plan* plan = nullptr;  // single-tree launch plan
 };
 
 // Launch plan: the work lists of one set of trees solved together.
 struct Plan {
   std::vector<smpc_tree*> trees;
-  int H = 0;
-  std::vector<int> lvl_off, lvl_cnt;
-  smpc::DevBuf items, td64, td32, refs, done;
+  int n_items = 0;  // leaf chains of all trees
+  smpc::DevBuf items, td64, td32, done;
   std::vector<int32_t> done_host;
   bool has32 = false;
   // instantiated graphs of `iters` iterations, keyed by (element size, mode, iters)

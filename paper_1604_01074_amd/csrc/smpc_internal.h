@@ -15,9 +15,7 @@
 //   z       M x (nx+nu)  primal iterate (x_n, u_n), written on check steps
 //   ctopQ/ctopR  per chain: state / input cost-to-go coefficients of the
 //                chain's top node, read by the parent chain's bottom node
-//   cbotX/cbotU  per chain: state / input-increment sum of the bottom node,
-//                read by the child chains' top nodes
-//   cstat   per chain: 4 float64 reduction partials
+//   cstat   per leaf chain: 4 float64 reduction partials
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -58,21 +56,14 @@ struct TreeState {
   int32_t check_every;  // residual test period
   int32_t status;       // 0 converged, 1 max_iter, -9 diverged
   int32_t iters_done;   // iterations when the tree stopped
-  int32_t pad0, pad1;
+  int32_t fwd_count;    // leaf chains finished in the current forward kernel
+  int32_t pad1;
   double tol;
   double lambda;
   double r_p;           // last ||Hz - t||_inf
   double hzt;           // last max(||Hz||_inf, ||t||_inf)
   double in_scale;      // power iteration: 1 / ||g_k||
   double lmax_est;      // power iteration: Rayleigh quotient
-};
-
-struct IterRef {
-  TreeState* st;
-  const double* cstat;
-  int32_t* done_out;   // done flag of tree `slot`, gathered for one host read
-  int32_t n_chains;
-  int32_t slot;
 };
 
 template <typename T>
@@ -104,29 +95,30 @@ struct TreeDev {
   T* z;
   T* ctopQ;
   T* ctopR;
-  T* cbotX;
-  T* cbotU;
   double* cstat;
   const ChainDesc* chains;
   TreeState* st;
+  int32_t* cnt;             // per chain: children whose backward sweep is done
+  const int32_t* leaves;    // the tree's leaf chains (height 0)
+  const int32_t* path_off;  // per chain: range of its ancestor chains in `path`
+  const int32_t* path;      // ancestor chains, root first; < 0 marks an ancestor
+                            // whose prox this leaf chain performs (-1 - id)
   int32_t n_chains;
+  int32_t n_leaves;
   int32_t M;
+  int32_t pad;
 };
 
-// Kernel launchers (smpc_kernels.hip).  `items` lists the chains of one
-// level across all trees of the launch; `trees` is a device table.
+// Kernel launchers (smpc_kernels.hip).  `items` lists the leaf chains of all
+// trees of the launch; `trees` is a device table.  One iteration is
+// launch_backward then launch_forward; `done_out[tree]` receives each tree's
+// stop flag at the end of the forward kernel.
 template <typename T>
 hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
                            int n_items, const double* ctab, int mode, hipStream_t s);
 template <typename T>
 hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
-                          int n_items, const double* ctab, int mode, hipStream_t s);
-// One workgroup per tree: folds the chain partials, applies the stop test
-// (or the power-iteration normalisation) and advances the iteration index.
-// `refs` is a device array of n_trees IterRef.
-hipError_t launch_iter_end_refs(const void* refs, int n_trees, int mode, hipStream_t s);
-template <typename T>
-hipError_t launch_convert_dual(const double* src, T* dst, size_t n, hipStream_t s);
+                          int n_items, const double* ctab, int mode, int32_t* done_out, hipStream_t s);
 template <typename T>
 hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s);
 

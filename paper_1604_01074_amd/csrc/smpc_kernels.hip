@@ -1,16 +1,22 @@
 // HIP kernels of the APG iteration for scenario-tree SMPC on gfx950.
 //
-// One iteration of eq. apg-iteration is, per level of the chain tree,
-//   k_backward  (leaf chains first):  extrapolation + backward sweep of the
-//                solve step (Alg. 1, first loop) over every chain of the level;
-//   k_forward   (root chain first):   forward rollout of the solve step (Alg. 1,
-//                second loop) fused with the prox of App. C and the dual update;
-//   k_iter_end  (one workgroup per tree): float64 residual reduction, stop
-//                test, iteration counter.
+// One iteration of eq. apg-iteration is two kernels over the leaf chains of
+// every tree of a launch (a chain is a maximal path of single-child nodes; a
+// leaf chain ends at a leaf):
 //
-// A chain is a maximal path of single-child nodes.  One workgroup walks one
-// chain, so the sequential stage dependence inside a chain never leaves the
-// workgroup; only the (few) branching levels need a kernel boundary.
+//   k_backward  extrapolation + the backward sweep of the solve step (Alg. 1,
+//               first loop).  A workgroup sweeps its leaf chain, hands the
+//               chain-top terms to the parent chain and counts itself done
+//               there; the workgroup that completes the last child sweeps the
+//               parent chain, and so on up to the root.  No workgroup waits.
+//   k_forward   the forward rollout (Alg. 1, second loop) fused with the prox
+//               of App. C and the dual update.  A workgroup first rebuilds the
+//               states along the root path of its leaf chain (prefix sums of
+//               the backward outputs) and applies the prox to the ancestor
+//               nodes it is designated for (each inner node has exactly one
+//               designated leaf chain), then rolls out its own chain.  The last
+//               workgroup of a tree folds the float64 partials, applies the
+//               stop test and advances the tree's iteration counter.
 //
 // The solve step is computed in input space rather than in the reduced
 // variables v of App. A: with P = L (L' Wu L)^{-1} L' (independent of the
@@ -21,7 +27,7 @@
 // and the forward rollout is
 //   ut_n = ut_{a(n)} + du_n,  u_n = ut_n + uhat_n,  x_n = A x_{a(n)} + B ut_n + e_n
 // which is Alg. 1 multiplied through by L (du_n = L dv_n, ut_n = L v_n).
-// B and A are applied in sparse (CSR) form; P is held in registers.
+// B and A are applied in sparse form; P is held in registers.
 #include "smpc_internal.h"
 
 namespace smpc {
@@ -52,6 +58,29 @@ __device__ __forceinline__ T clampv(T a, T lo, T hi) {
   return a < lo ? lo : (a > hi ? hi : a);
 }
 
+// Values handed between workgroups of one launch (chain-top terms, reduction
+// partials, counters) travel through agent-scope atomic loads and stores,
+// which gfx950 keeps coherent across its XCDs without writing back or
+// invalidating a whole L2 (what a device-scope fence does).
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T* p) {
+  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until this wave's memory operations have completed (stores
+// acknowledged at the coherence point), so that a counter increment issued
+// after the following barrier is seen only after them.
+__device__ __forceinline__ void wait_mem() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Dynamic LDS: 32 float64 reduction slots, then T-typed arrays.
 constexpr int kRedDoubles = 32;
 
@@ -63,6 +92,78 @@ template <typename T>
 struct Chunk {
   static constexpr int value = sizeof(T) == 4 ? 24 : 12;
 };
+
+// Loads per thread and array issued in one staging batch, before any LDS
+// store (halved in float64 to leave registers for the P slice).
+template <typename T>
+struct Stage {
+  static constexpr int Y = sizeof(T) == 4 ? 12 : 6;
+  static constexpr int U = sizeof(T) == 4 ? 6 : 3;
+  static constexpr int X = sizeof(T) == 4 ? 4 : 2;
+};
+
+// Sparse rows kept in registers: unused slots have weight 0 and index 0.
+constexpr int kNnzBt = 4;  // B' rows: a flow touches few tanks
+constexpr int kNnzB = 8;   // B rows: a tank is touched by few flows
+
+template <typename T, int K>
+struct RowCache {
+  int c[K];
+  T w[K];
+  int n, q0, q1;
+};
+
+template <typename T, int K>
+__device__ __forceinline__ void load_row(RowCache<T, K>& r, const int32_t* rp, const int32_t* ci, const T* v,
+                                         int row, bool valid) {
+  r.n = r.q0 = r.q1 = 0;
+  if (valid) {
+    r.q0 = rp[row];
+    r.q1 = rp[row + 1];
+    r.n = r.q1 - r.q0;
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    r.c[q] = q < r.n ? ci[r.q0 + q] : 0;
+    r.w[q] = q < r.n ? v[r.q0 + q] : T(0);
+  }
+}
+
+// Per-workgroup view of one iteration of one tree.
+template <typename T>
+struct Iter {
+  int it;
+  T c, in_scale, lam, ilam;
+  bool affine, scaled, write_z;
+  const T* ycur;
+  const T* yprv;
+  T* ynew;
+};
+
+template <typename T>
+__device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const TreeState* st, const double* ctab,
+                                             int mode) {
+  Iter<T> x;
+  x.it = st->iter;
+  x.c = T(0);
+  x.in_scale = T(1);
+  x.lam = T(1);
+  x.ilam = T(1);
+  if (mode == kModeAPG) {
+    x.c = (T)ctab[x.it];
+    x.lam = (T)st->lambda;
+    x.ilam = T(1) / x.lam;
+  }
+  if (mode == kModePower) x.in_scale = (T)st->in_scale;
+  x.affine = mode != kModePower;
+  x.scaled = (td.scale != nullptr) && (mode != kModeSolve);
+  const bool check = (mode != kModeAPG) || ((x.it + 1) % st->check_every == 0) || (x.it + 1 >= st->max_iter);
+  x.write_z = (mode == kModeSolve) || (mode == kModeAPG && check);
+  x.ycur = td.y[x.it % 3];
+  x.yprv = td.y[(x.it + 2) % 3];
+  x.ynew = td.y[(x.it + 1) % 3];
+  return x;
+}
 
 }  // namespace
 
@@ -84,53 +185,31 @@ size_t lds_bytes_forward(int nx, int nu, size_t elem) {
   return kRedDoubles * sizeof(double) + elem * (ch * (D + 2 * nu + nx + 4) + nx + nu);
 }
 
-// Loads per thread and array issued in one staging batch, before any LDS
-// store (halved in float64 to leave registers for the P slice).
-template <typename T>
-struct Stage {
-  static constexpr int Y = sizeof(T) == 4 ? 12 : 6;
-  static constexpr int U = sizeof(T) == 4 ? 6 : 3;
-  static constexpr int X = sizeof(T) == 4 ? 4 : 2;
-};
-
 namespace {
 
 // ---------------------------------------------------------------------------
 // backward sweep of one chain
 //
-// Per chunk (bottom-up): load xi_n = S(w_sigma + w_zeta) and
-// r_n = beta_n + S w_psi of all its nodes at once; run the recursions
-// Q_n = xi_n + A' Q_below and rho_n = r_n + B' Q_n + rho_below as per-component
-// scans (one thread per component when A = I); then du_n = -P rho_n / (2 pi_n)
-// for all nodes of the chunk with P held in registers: thread (j, h) keeps
-// P[j][h*KH .. h*KH + KH) and the S k-parts of a row sit in adjacent lanes,
-// so the partial sums combine with lane shuffles.
+// Per chunk (bottom-up): stage w = y + c (y - y_prev) and beta of the chunk's
+// nodes (consecutive in memory) with batched loads; form xi_n = S(w_sigma +
+// w_zeta) and r_n = beta_n + S w_psi; run Q_n = xi_n + A' Q_below and
+// rho_n = r_n + B' Q_n + rho_below as per-component scans (one thread per
+// component when A = I); then du_n = -P rho_n / (2 pi_n) for the whole chunk
+// with P held in registers: thread (j, h) keeps P[j][h*KH .. h*KH + KH), the
+// S k-parts of a row sit in adjacent lanes and combine with lane shuffles.
 // ---------------------------------------------------------------------------
 template <typename T, int S, int KH>
-__global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
-                                                     const WorkItem* __restrict__ items,
-                                                     const double* __restrict__ ctab, int mode) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int tid = threadIdx.x;
-  const WorkItem wi = items[blockIdx.x];
-  const TreeDev<T>& td = trees[wi.tree];
-  const TreeState* st = td.st;
-  if (st->done) return;
-  const int it = st->iter;
-  const ChainDesc ch = td.chains[wi.chain];
-  const int nx = sys.nx, nu = sys.nu, D = sys.D;
-
-  T c = T(0), in_scale = T(1);
-  if (mode == kModeAPG) c = (T)ctab[it];
-  if (mode == kModePower) in_scale = (T)st->in_scale;
-  const bool affine = (mode != kModePower);
-  const bool scaled = (td.scale != nullptr) && (mode != kModeSolve);
-  const T* __restrict__ ycur = td.y[it % 3];
-  const T* __restrict__ yprv = td.y[(it + 2) % 3];
-
+__device__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode, int chain,
+                          unsigned char* smem_raw, const T (&preg)[KH], const RowCache<T, kNnzBt>& bt) {
   constexpr int kChunk = Chunk<T>::value;
   constexpr int kStageY = Stage<T>::Y, kStageU = Stage<T>::U;
-  constexpr int KP = S * KH;  // padded P stride and rho row stride
+  constexpr int KP = S * KH;
+  const int tid = threadIdx.x;
+  const int nx = sys.nx, nu = sys.nu, D = sys.D;
+  const ChainDesc ch = td.chains[chain];
+  const int pj = tid / S;
+  const int ph = tid % S;
+
   T* sW = reinterpret_cast<T*>(smem_raw + kRedDoubles * sizeof(double));  // kChunk x D
   T* sB = sW + (size_t)kChunk * D;                                        // kChunk x nu
   T* sQ = sB + (size_t)kChunk * nu;                                       // kChunk x nx
@@ -140,55 +219,29 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
   T* sQc = sS + 3 * kChunk;
   T* sRc = sQc + nx;
 
-  // P slice of this thread (P is stored zero-padded to KP x KP)
-  const int pj = tid / S;
-  const int ph = tid % S;
-  T preg[KH];
-#pragma unroll
-  for (int kk = 0; kk < KH; ++kk) preg[kk] = sys.P[(size_t)(ph * KH + kk) * KP + pj];
-  for (int e = tid; e < kChunk * (KP - nu); e += kBlock) {
-    const int cc = e / (KP - nu);
-    sR[cc * KP + nu + (e - cc * (KP - nu))] = T(0);
-  }
-  // this thread's sparse row of B' (a flow touches few tanks), kept in
-  // registers; unused slots have weight 0 and index 0
-  constexpr int kNnz = 4;
-  int bt_c[kNnz];
-  T bt_w[kNnz];
-  int bt_n = 0, bt_q0 = 0, bt_q1 = 0;
-  if (tid < nu) {
-    bt_q0 = sys.bt_rp[tid];
-    bt_q1 = sys.bt_rp[tid + 1];
-    bt_n = bt_q1 - bt_q0;
-  }
-#pragma unroll
-  for (int q = 0; q < kNnz; ++q) {
-    bt_c[q] = q < bt_n ? sys.bt_ci[bt_q0 + q] : 0;
-    bt_w[q] = q < bt_n ? sys.bt_v[bt_q0 + q] : T(0);
-  }
-
   // cost-to-go terms handed up by the child chains of the bottom node
   for (int i = tid; i < nx; i += kBlock) {
     T acc = T(0);
-    for (int cc = 0; cc < ch.child_count; ++cc) acc += td.ctopQ[(size_t)(ch.child_begin + cc) * nx + i];
+    for (int k = 0; k < ch.child_count; ++k) acc += ld_agent(&td.ctopQ[(size_t)(ch.child_begin + k) * nx + i]);
     sQc[i] = acc;
   }
   for (int j = tid; j < nu; j += kBlock) {
     T acc = T(0);
-    for (int cc = 0; cc < ch.child_count; ++cc) acc += td.ctopR[(size_t)(ch.child_begin + cc) * nu + j];
+    for (int k = 0; k < ch.child_count; ++k) acc += ld_agent(&td.ctopR[(size_t)(ch.child_begin + k) * nu + j]);
     sRc[j] = acc;
   }
+  for (int e = tid; e < kChunk * (KP - nu); e += kBlock) {
+    const int cc = e / (KP - nu);
+    sR[cc * KP + nu + (e - cc * (KP - nu))] = T(0);
+  }
 
-  const int W = nx + nu;
   for (int top = ch.len; top > 0; top -= kChunk) {
     const int k0 = top > kChunk ? top - kChunk : 0;
     const int C = top - k0;
     const int nb = ch.first + k0;  // internal index of the chunk's first node
-    // stage the chunk: its nodes are consecutive, so y, y_prev and beta are
-    // contiguous ranges; every batch issues all its loads before any store
     {
       const int ny = C * D;
-      const int nbt = affine ? C * nu : 0;
+      const int nbt = x.affine ? C * nu : 0;
       const size_t oy = (size_t)nb * D, ob = (size_t)nb * nu;
       for (int b = 0; b * kStageY * kBlock < ny || b * kStageU * kBlock < nbt; ++b) {
         T ry[kStageY], rp[kStageY], rb[kStageU];
@@ -196,8 +249,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
 #pragma unroll
         for (int u = 0; u < kStageY; ++u) {
           const int e = (b * kStageY + u) * kBlock + tid;
-          ry[u] = e < ny ? ycur[oy + e] : T(0);
-          rp[u] = (mode == kModeAPG && e < ny) ? yprv[oy + e] : T(0);
+          ry[u] = e < ny ? x.ycur[oy + e] : T(0);
+          rp[u] = (mode == kModeAPG && e < ny) ? x.yprv[oy + e] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < kStageU; ++u) {
@@ -205,7 +258,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
           rb[u] = e < nbt ? td.beta[ob + e] : T(0);
         }
         if (b == 0) {
-          if (tid < 3 * C && scaled) rs = td.scale[(size_t)nb * 3 + tid];
+          if (tid < 3 * C && x.scaled) rs = td.scale[(size_t)nb * 3 + tid];
           if (tid < C) rpi = td.pi[nb + tid];
         }
 #pragma unroll
@@ -213,7 +266,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
           const int e = (b * kStageY + u) * kBlock + tid;
           if (e < ny) {
             const T y = ry[u];
-            sW[e] = mode == kModeAPG ? y + c * (y - rp[u]) : (mode == kModePower ? in_scale * y : y);
+            sW[e] = mode == kModeAPG ? y + x.c * (y - rp[u]) : (mode == kModePower ? x.in_scale * y : y);
           }
         }
 #pragma unroll
@@ -228,7 +281,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
       }
     }
     __syncthreads();
-    // xi = S(w_sigma + w_zeta) and r = beta + S w_psi from LDS
+    // xi = S(w_sigma + w_zeta) and r = beta + S w_psi
     for (int e = tid; e < C * nx; e += kBlock) {
       const int cc = e / nx;
       const int i = e - cc * nx;
@@ -237,56 +290,54 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
     for (int e = tid; e < C * nu; e += kBlock) {
       const int cc = e / nu;
       const int j = e - cc * nu;
-      sR[cc * KP + j] = (affine ? sB[e] : T(0)) + sS[3 * cc + 2] * sW[cc * D + 2 * nx + j];
+      sR[cc * KP + j] = (x.affine ? sB[e] : T(0)) + sS[3 * cc + 2] * sW[cc * D + 2 * nx + j];
     }
     __syncthreads();
     // Q recursion, bottom node of the chunk first
     if (sys.a_identity) {
-      for (int i = tid; i < nx; i += kBlock) {
-        T q = sQc[i];
+      if (tid < nx) {
+        T q = sQc[tid];
         for (int cc = C - 1; cc >= 0; --cc) {
-          q += sQ[cc * nx + i];
-          sQ[cc * nx + i] = q;
+          q += sQ[cc * nx + tid];
+          sQ[cc * nx + tid] = q;
         }
-        sQc[i] = q;
+        sQc[tid] = q;
       }
     } else {
       for (int cc = C - 1; cc >= 0; --cc) {
-        for (int i = tid; i < nx; i += kBlock) {
-          T q = sQ[cc * nx + i];
-          for (int r = sys.at_rp[i]; r < sys.at_rp[i + 1]; ++r) q += sys.at_v[r] * sQc[sys.at_ci[r]];
-          sQ[cc * nx + i] = q;
+        if (tid < nx) {
+          T q = sQ[cc * nx + tid];
+          for (int r = sys.at_rp[tid]; r < sys.at_rp[tid + 1]; ++r) q += sys.at_v[r] * sQc[sys.at_ci[r]];
+          sQ[cc * nx + tid] = q;
         }
         __syncthreads();
-        for (int i = tid; i < nx; i += kBlock) sQc[i] = sQ[cc * nx + i];
+        if (tid < nx) sQc[tid] = sQ[cc * nx + tid];
         __syncthreads();
       }
     }
     __syncthreads();
-    // rho recursion (one thread per input component; nu <= kBlock)
+    // rho recursion (one thread per input component)
     if (tid < nu) {
-      const int j = tid;
-      T r = sRc[j];
+      T r = sRc[tid];
       for (int cc = C - 1; cc >= 0; --cc) {
-        T g = sR[cc * KP + j];
-        if (bt_n <= kNnz) {
+        T g = sR[cc * KP + tid];
+        if (bt.n <= kNnzBt) {
 #pragma unroll
-          for (int q = 0; q < kNnz; ++q) g += bt_w[q] * sQ[cc * nx + bt_c[q]];
+          for (int q = 0; q < kNnzBt; ++q) g += bt.w[q] * sQ[cc * nx + bt.c[q]];
         } else {
-          for (int q = bt_q0; q < bt_q1; ++q) g += sys.bt_v[q] * sQ[cc * nx + sys.bt_ci[q]];
+          for (int q = bt.q0; q < bt.q1; ++q) g += sys.bt_v[q] * sQ[cc * nx + sys.bt_ci[q]];
         }
         r += g;
-        sR[cc * KP + j] = r;
+        sR[cc * KP + tid] = r;
       }
-      sRc[j] = r;
+      sRc[tid] = r;
     }
     __syncthreads();
-    // du = -P rho / (2 pi) for the chunk
+    // du = -P rho / (2 pi): branch-free; padded entries of P and rho are zero,
+    // rows cc >= C are computed from stale finite values and not stored
     T acc[kChunk];
 #pragma unroll
     for (int cc = 0; cc < kChunk; ++cc) acc[cc] = T(0);
-    // branch-free: padded entries of P and rho are zero, rows cc >= C are
-    // computed from stale finite values and not stored
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
       const T pv = preg[kk];
@@ -309,55 +360,83 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
     __syncthreads();
   }
   // top node of the chain: hand Q and rho to the parent chain
-  for (int i = tid; i < nx; i += kBlock) td.ctopQ[(size_t)wi.chain * nx + i] = sQc[i];
-  for (int j = tid; j < nu; j += kBlock) td.ctopR[(size_t)wi.chain * nu + j] = sRc[j];
+  for (int i = tid; i < nx; i += kBlock) st_agent(&td.ctopQ[(size_t)chain * nx + i], sQc[i]);
+  for (int j = tid; j < nu; j += kBlock) st_agent(&td.ctopR[(size_t)chain * nu + j], sRc[j]);
 }
 
-// ---------------------------------------------------------------------------
-// forward rollout of one chain, fused with prox and dual update
-//
-// Per chunk (top-down): stage the dual point w, du, uhat and e of all its
-// nodes in LDS with one round of wide loads, run the recursions
-// ut_n = ut_above + du_n and x_n = A x_above + B ut_n + e_n as per-component
-// scans, then the prox (App. C) and the dual update for every entry of the
-// chunk: each (node, sigma|zeta) block is handled by one wave with its
-// Euclidean norm reduced by lane shuffles, the psi entries are spread over all
-// threads.  NXL = ceil(nx / 64) entries per lane of a distance block.
-// ---------------------------------------------------------------------------
-template <typename T, int NXL>
-__global__ __launch_bounds__(kBlock) void k_forward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
-                                                    const WorkItem* __restrict__ items,
-                                                    const double* __restrict__ ctab, int mode) {
+template <typename T, int S, int KH>
+__global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
+                                                        const WorkItem* __restrict__ items,
+                                                        const double* __restrict__ ctab, int mode) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int kChunk = Chunk<T>::value;
-  constexpr int kStageY = Stage<T>::Y, kStageU = Stage<T>::U, kStageX = Stage<T>::X;
-  constexpr int kWaves = kBlock / 64;
-  double* sRed = reinterpret_cast<double*>(smem_raw);
+  __shared__ int s_last;
+  constexpr int KP = S * KH;
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
   const WorkItem wi = items[blockIdx.x];
   const TreeDev<T>& td = trees[wi.tree];
   const TreeState* st = td.st;
   if (st->done) return;
-  const int it = st->iter;
-  const ChainDesc ch = td.chains[wi.chain];
-  const int nx = sys.nx, nu = sys.nu, D = sys.D;
-  const bool affine = (mode != kModePower);
-  const bool scaled = (td.scale != nullptr) && (mode != kModeSolve);
-  const bool check = (mode != kModeAPG) || ((it + 1) % st->check_every == 0) || (it + 1 >= st->max_iter);
-  const bool write_z = (mode == kModeSolve) || (mode == kModeAPG && check);
+  const Iter<T> x = make_iter(td, st, ctab, mode);
+  const int nu = sys.nu;
 
-  T c = T(0), in_scale = T(1), lam = T(1), ilam = T(1);
-  if (mode == kModeAPG) {
-    c = (T)ctab[it];
-    lam = (T)st->lambda;
-    ilam = T(1) / lam;
+  // P slice of this thread (P is stored zero-padded to KP x KP)
+  T preg[KH];
+  {
+    const int pj = tid / S;
+    const int ph = tid % S;
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) preg[kk] = sys.P[(size_t)(ph * KH + kk) * KP + pj];
   }
-  if (mode == kModePower) in_scale = (T)st->in_scale;
-  const T* __restrict__ ycur = td.y[it % 3];
-  const T* __restrict__ yprv = td.y[(it + 2) % 3];
-  T* __restrict__ ynew = td.y[(it + 1) % 3];
+  RowCache<T, kNnzBt> bt;
+  load_row(bt, sys.bt_rp, sys.bt_ci, sys.bt_v, tid, tid < nu);
+
+  int chain = wi.chain;
+  while (true) {
+    bwd_chain<T, S, KH>(sys, td, x, mode, chain, smem_raw, preg, bt);
+    const int parent = td.chains[chain].parent;
+    if (parent < 0) break;  // the root chain is done: the sweep is complete
+    // this chain's top terms are stored: count this child done at the parent
+    wait_mem();
+    __syncthreads();
+    if (tid == 0) {
+      const int pc = td.chains[parent].child_count;
+      const int prev = __hip_atomic_fetch_add(&td.cnt[parent], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_last = (prev == pc - 1);
+      if (s_last) st_agent(&td.cnt[parent], 0);  // ready for the next iteration
+    }
+    __syncthreads();
+    if (!s_last) break;  // a sibling is still running; it will sweep the parent
+    chain = parent;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward rollout and prox of consecutive nodes [first, first + len)
+//
+// The carries sXc / sUc hold the state x and input increment ut of the node
+// above.  With do_prox the nodes' prox, dual update and primal output are
+// computed; otherwise only the recursion runs (an ancestor another leaf chain
+// owns).  Per chunk: stage w, du, uhat, e (consecutive nodes: contiguous
+// ranges) with batched loads, run ut_n = ut_above + du_n and
+// x_n = A x_above + B ut_n + e_n as per-component scans, then the prox: each
+// (node, sigma|zeta) block is one wave with its Euclidean norm reduced by lane
+// shuffles, the psi entries are spread over all threads.
+// ---------------------------------------------------------------------------
+template <typename T, int NXL>
+__device__ void fwd_segment(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode, int first,
+                            int len, bool do_prox, unsigned char* smem_raw, const RowCache<T, kNnzB>& brow,
+                            double& st0, double& st1, double& st2) {
+  constexpr int kChunk = Chunk<T>::value;
+  constexpr int kStageY = Stage<T>::Y, kStageU = Stage<T>::U, kStageX = Stage<T>::X;
+  constexpr int kWaves = kBlock / 64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nx = sys.nx, nu = sys.nu, D = sys.D;
+  const int W = nx + nu;
+  const T cSx = (T)sys.W_x;
+  const T gam_d = (T)sys.gamma_d;
+  const bool prox = do_prox && mode != kModeSolve;
 
   T* sW = reinterpret_cast<T*>(smem_raw + kRedDoubles * sizeof(double));  // kChunk x D
   T* sU = sW + (size_t)kChunk * D;                                        // kChunk x nu
@@ -368,45 +447,14 @@ __global__ __launch_bounds__(kBlock) void k_forward(SysDev<T> sys, const TreeDev
   T* sUc = sS + 3 * kChunk;
   T* sXc = sUc + nu;
 
-  if (ch.parent < 0) {
-    for (int i = tid; i < nx; i += kBlock) sXc[i] = affine ? td.p[i] : T(0);
-    for (int j = tid; j < nu; j += kBlock) sUc[j] = T(0);
-  } else {
-    for (int i = tid; i < nx; i += kBlock) sXc[i] = td.cbotX[(size_t)ch.parent * nx + i];
-    for (int j = tid; j < nu; j += kBlock) sUc[j] = td.cbotU[(size_t)ch.parent * nu + j];
-  }
-  const T cSx = (T)sys.W_x;
-  const T gam_d = (T)sys.gamma_d;
-  double st0 = 0.0, st1 = 0.0, st2 = 0.0;  // residual / |Hz| / |t| maxima, or power sums
-  const int W = nx + nu;
-  const int L1 = D + 2 * nu + nx;  // staged values per node
-  // this thread's sparse row of B (a tank is touched by few flows); unused
-  // slots have weight 0 and index 0
-  constexpr int kNnz = 8;
-  int b_c[kNnz];
-  T b_w[kNnz];
-  int b_n = 0, b_r0 = 0, b_r1 = 0;
-  if (tid < nx) {
-    b_r0 = sys.b_rp[tid];
-    b_r1 = sys.b_rp[tid + 1];
-    b_n = b_r1 - b_r0;
-  }
-#pragma unroll
-  for (int r = 0; r < kNnz; ++r) {
-    b_c[r] = r < b_n ? sys.b_ci[b_r0 + r] : 0;
-    b_w[r] = r < b_n ? sys.b_v[b_r0 + r] : T(0);
-  }
-
-  for (int k0 = 0; k0 < ch.len; k0 += kChunk) {
-    const int C = ch.len - k0 < kChunk ? ch.len - k0 : kChunk;
-    const int nb = ch.first + k0;
-    // stage the chunk (consecutive nodes: contiguous ranges of y, y_prev,
-    // du, uhat, e); every batch issues all its loads before any store
+  for (int k0 = 0; k0 < len; k0 += kChunk) {
+    const int C = len - k0 < kChunk ? len - k0 : kChunk;
+    const int nb = first + k0;
     {
-      const int ny = mode == kModeSolve ? 0 : C * D;
+      const int ny = prox ? C * D : 0;
       const int nuu = C * nu;
-      const int nh = affine ? C * nu : 0;
-      const int ne = affine ? C * nx : 0;
+      const int nh = (x.affine && do_prox) ? C * nu : 0;
+      const int ne = x.affine ? C * nx : 0;
       const size_t oy = (size_t)nb * D, ou = (size_t)nb * nu, ox = (size_t)nb * nx;
       for (int b = 0; b * kStageY * kBlock < ny || b * kStageU * kBlock < nuu || b * kStageX * kBlock < C * nx;
            ++b) {
@@ -415,8 +463,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(SysDev<T> sys, const TreeDev
 #pragma unroll
         for (int u = 0; u < kStageY; ++u) {
           const int e = (b * kStageY + u) * kBlock + tid;
-          ry[u] = e < ny ? ycur[oy + e] : T(0);
-          rp[u] = (mode == kModeAPG && e < ny) ? yprv[oy + e] : T(0);
+          ry[u] = e < ny ? x.ycur[oy + e] : T(0);
+          rp[u] = (mode == kModeAPG && e < ny) ? x.yprv[oy + e] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < kStageU; ++u) {
@@ -429,8 +477,8 @@ __global__ __launch_bounds__(kBlock) void k_forward(SysDev<T> sys, const TreeDev
           const int e = (b * kStageX + u) * kBlock + tid;
           rx[u] = e < ne ? td.e[ox + e] : T(0);
         }
-        if (b == 0) {
-          if (tid < 3 * C && scaled) rs = td.scale[(size_t)nb * 3 + tid];
+        if (b == 0 && prox) {
+          if (tid < 3 * C && x.scaled) rs = td.scale[(size_t)nb * 3 + tid];
           if (tid < C) rpi = td.pi[nb + tid];
         }
 #pragma unroll
@@ -438,7 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(SysDev<T> sys, const TreeDev
           const int e = (b * kStageY + u) * kBlock + tid;
           if (e < ny) {
             const T y = ry[u];
-            sW[e] = mode == kModeAPG ? y + c * (y - rp[u]) : in_scale * y;
+            sW[e] = mode == kModeAPG ? y + x.c * (y - rp[u]) : x.in_scale * y;
           }
         }
 #pragma unroll
@@ -462,131 +510,172 @@ __global__ __launch_bounds__(kBlock) void k_forward(SysDev<T> sys, const TreeDev
     }
     __syncthreads();
     // ut recursion (top node of the chunk first)
-    for (int j = tid; j < nu; j += kBlock) {
-      T u = sUc[j];
+    if (tid < nu) {
+      T u = sUc[tid];
       for (int cc = 0; cc < C; ++cc) {
-        u += sU[cc * nu + j];
-        sU[cc * nu + j] = u;
+        u += sU[cc * nu + tid];
+        sU[cc * nu + tid] = u;
       }
-      sUc[j] = u;
+      sUc[tid] = u;
     }
     __syncthreads();
-    // x recursion (one thread per state component; nx <= kBlock)
+    // x recursion
     if (sys.a_identity) {
       if (tid < nx) {
-        const int i = tid;
-        T x = sXc[i];
+        T xv = sXc[tid];
         for (int cc = 0; cc < C; ++cc) {
-          T g = sX[cc * nx + i];
-          if (b_n <= kNnz) {
+          T g = sX[cc * nx + tid];
+          if (brow.n <= kNnzB) {
 #pragma unroll
-            for (int r = 0; r < kNnz; ++r) g += b_w[r] * sU[cc * nu + b_c[r]];
+            for (int r = 0; r < kNnzB; ++r) g += brow.w[r] * sU[cc * nu + brow.c[r]];
           } else {
-            for (int r = b_r0; r < b_r1; ++r) g += sys.b_v[r] * sU[cc * nu + sys.b_ci[r]];
+            for (int r = brow.q0; r < brow.q1; ++r) g += sys.b_v[r] * sU[cc * nu + sys.b_ci[r]];
           }
-          x += g;
-          sX[cc * nx + i] = x;
+          xv += g;
+          sX[cc * nx + tid] = xv;
         }
-        sXc[i] = x;
+        sXc[tid] = xv;
       }
     } else {
       for (int cc = 0; cc < C; ++cc) {
-        for (int i = tid; i < nx; i += kBlock) {
-          T x = sX[cc * nx + i];
-          for (int r = sys.a_rp[i]; r < sys.a_rp[i + 1]; ++r) x += sys.a_v[r] * sXc[sys.a_ci[r]];
-          for (int r = sys.b_rp[i]; r < sys.b_rp[i + 1]; ++r) x += sys.b_v[r] * sU[cc * nu + sys.b_ci[r]];
-          sX[cc * nx + i] = x;
+        if (tid < nx) {
+          T xv = sX[cc * nx + tid];
+          for (int r = sys.a_rp[tid]; r < sys.a_rp[tid + 1]; ++r) xv += sys.a_v[r] * sXc[sys.a_ci[r]];
+          for (int r = sys.b_rp[tid]; r < sys.b_rp[tid + 1]; ++r) xv += sys.b_v[r] * sU[cc * nu + sys.b_ci[r]];
+          sX[cc * nx + tid] = xv;
         }
         __syncthreads();
-        for (int i = tid; i < nx; i += kBlock) sXc[i] = sX[cc * nx + i];
+        if (tid < nx) sXc[tid] = sX[cc * nx + tid];
         __syncthreads();
       }
     }
     __syncthreads();
 
-    // distance blocks: one wave per (node, block)
-    for (int p = wave; p < 2 * C; p += kWaves) {  // wave-uniform loop
-      const int cc = p >> 1;
-      const int b = p & 1;
-      const size_t n = (size_t)(nb + cc);
-      const T s = sS[3 * cc + b];
-      T a_[NXL], pa_[NXL], hz_[NXL];
-      T dsq = T(0);
+    if (do_prox) {
+      // distance blocks: one wave per (node, block)
+      for (int p = wave; p < 2 * C; p += kWaves) {  // wave-uniform loop
+        const int cc = p >> 1;
+        const int b = p & 1;
+        const size_t n = (size_t)(nb + cc);
+        const T s = sS[3 * cc + b];
+        T a_[NXL], pa_[NXL], hz_[NXL];
+        T dsq = T(0);
 #pragma unroll
-      for (int r = 0; r < NXL; ++r) {
-        const int i = lane + 64 * r;
-        a_[r] = pa_[r] = hz_[r] = T(0);
-        if (i < nx) {
-          const T hzv = sX[cc * nx + i];
-          hz_[r] = hzv;
-          if (write_z && b == 0) td.z[n * W + i] = hzv;
-          if (mode == kModePower) {
-            const T g = -s * hzv;
-            ynew[n * D + b * nx + i] = g;
-            st0 += (double)g * (double)g;
-            st1 += (double)sW[cc * D + b * nx + i] * (double)g;
-          } else if (mode == kModeAPG) {
-            const T w = sW[cc * D + b * nx + i];
-            const T a = (w * ilam + s * hzv) / s;
-            const T pa = b == 0 ? (a > sys.xs[i] ? a : sys.xs[i]) : clampv(a, sys.xmin[i], sys.xmax[i]);
-            const T dd = a - pa;
-            dsq += dd * dd;
-            a_[r] = a;
-            pa_[r] = pa;
+        for (int r = 0; r < NXL; ++r) {
+          const int i = lane + 64 * r;
+          a_[r] = pa_[r] = hz_[r] = T(0);
+          if (i < nx) {
+            const T hzv = sX[cc * nx + i];
+            hz_[r] = hzv;
+            if (x.write_z && b == 0) td.z[n * W + i] = hzv;
+            if (mode == kModePower) {
+              const T g = -s * hzv;
+              x.ynew[n * D + b * nx + i] = g;
+              st0 += (double)g * (double)g;
+              st1 += (double)sW[cc * D + b * nx + i] * (double)g;
+            } else if (mode == kModeAPG) {
+              const T w = sW[cc * D + b * nx + i];
+              const T a = (w * x.ilam + s * hzv) / s;
+              const T pa = b == 0 ? (a > sys.xs[i] ? a : sys.xs[i]) : clampv(a, sys.xmin[i], sys.xmax[i]);
+              const T dd = a - pa;
+              dsq += dd * dd;
+              a_[r] = a;
+              pa_[r] = pa;
+            }
+          }
+        }
+        if (mode != kModeAPG) continue;
+        dsq = wave_sum(dsq);
+        const T del = sqrt(dsq);
+        const T cb = b == 0 ? (sys.safety_by_prob ? cSx * sPi[cc] : cSx) : gam_d;
+        const T tau = cb * x.ilam / (s * s);
+#pragma unroll
+        for (int r = 0; r < NXL; ++r) {
+          const int i = lane + 64 * r;
+          if (i < nx) {
+            const T a = a_[r], pa = pa_[r];
+            const T tun = del <= tau ? pa : a - (tau / del) * (a - pa);
+            const T hzv = hz_[r];
+            x.ynew[n * D + b * nx + i] = sW[cc * D + b * nx + i] + x.lam * (s * hzv - s * tun);
+            st0 = nanmax(st0, fabs((double)hzv - (double)tun));
+            st1 = nanmax(st1, fabs((double)hzv));
+            st2 = nanmax(st2, fabs((double)tun));
           }
         }
       }
-      if (mode != kModeAPG) continue;
-      dsq = wave_sum(dsq);
-      const T del = sqrt(dsq);
-      const T cb = b == 0 ? (sys.safety_by_prob ? cSx * sPi[cc] : cSx) : gam_d;
-      const T tau = cb * ilam / (s * s);
-#pragma unroll
-      for (int r = 0; r < NXL; ++r) {
-        const int i = lane + 64 * r;
-        if (i < nx) {
-          const T a = a_[r], pa = pa_[r];
-          const T tun = del <= tau ? pa : a - (tau / del) * (a - pa);
-          const T hzv = hz_[r];
-          ynew[n * D + b * nx + i] = sW[cc * D + b * nx + i] + lam * (s * hzv - s * tun);
-          st0 = nanmax(st0, fabs((double)hzv - (double)tun));
-          st1 = nanmax(st1, fabs((double)hzv));
-          st2 = nanmax(st2, fabs((double)tun));
+      // psi blocks: input box
+      for (int e = tid; e < C * nu; e += kBlock) {
+        const int cc = e / nu;
+        const int j = e - cc * nu;
+        const size_t n = (size_t)(nb + cc);
+        const T u = sU[cc * nu + j] + sH[cc * nu + j];
+        if (x.write_z) td.z[n * W + nx + j] = u;
+        if (mode == kModeSolve) continue;
+        const T s = sS[3 * cc + 2];
+        const T w = sW[cc * D + 2 * nx + j];
+        if (mode == kModePower) {
+          const T g = -s * u;
+          x.ynew[n * D + 2 * nx + j] = g;
+          st0 += (double)g * (double)g;
+          st1 += (double)w * (double)g;
+          continue;
         }
+        const T a = (w * x.ilam + s * u) / s;
+        const T tun = clampv(a, sys.umin[j], sys.umax[j]);
+        x.ynew[n * D + 2 * nx + j] = w + x.lam * (s * u - s * tun);
+        st0 = nanmax(st0, fabs((double)u - (double)tun));
+        st1 = nanmax(st1, fabs((double)u));
+        st2 = nanmax(st2, fabs((double)tun));
       }
-    }
-    // psi blocks: input box
-    for (int e = tid; e < C * nu; e += kBlock) {
-      const int cc = e / nu;
-      const int j = e - cc * nu;
-      const size_t n = (size_t)(nb + cc);
-      const T u = sU[cc * nu + j] + sH[cc * nu + j];
-      if (write_z) td.z[n * W + nx + j] = u;
-      if (mode == kModeSolve) continue;
-      const T s = sS[3 * cc + 2];
-      const T w = sW[cc * D + 2 * nx + j];
-      if (mode == kModePower) {
-        const T g = -s * u;
-        ynew[n * D + 2 * nx + j] = g;
-        st0 += (double)g * (double)g;
-        st1 += (double)w * (double)g;
-        continue;
-      }
-      const T a = (w * ilam + s * u) / s;
-      const T tun = clampv(a, sys.umin[j], sys.umax[j]);
-      ynew[n * D + 2 * nx + j] = w + lam * (s * u - s * tun);
-      st0 = nanmax(st0, fabs((double)u - (double)tun));
-      st1 = nanmax(st1, fabs((double)u));
-      st2 = nanmax(st2, fabs((double)tun));
     }
     __syncthreads();
   }
-  // bottom node of the chain: hand x and ut to the child chains
-  if (ch.child_count > 0) {
-    for (int i = tid; i < nx; i += kBlock) td.cbotX[(size_t)wi.chain * nx + i] = sXc[i];
-    for (int j = tid; j < nu; j += kBlock) td.cbotU[(size_t)wi.chain * nu + j] = sUc[j];
+}
+
+template <typename T, int NXL>
+__global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
+                                                       const WorkItem* __restrict__ items,
+                                                       const double* __restrict__ ctab, int mode,
+                                                       int32_t* __restrict__ done_out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_last;
+  double* sRed = reinterpret_cast<double*>(smem_raw);
+  constexpr int kChunk = Chunk<T>::value;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const WorkItem wi = items[blockIdx.x];
+  const TreeDev<T>& td = trees[wi.tree];
+  TreeState* st = td.st;
+  if (st->done) {
+    if (tid == 0) done_out[wi.tree] = 1;
+    return;
   }
-  // chain partials
+  const Iter<T> x = make_iter(td, st, ctab, mode);
+  const int nx = sys.nx, nu = sys.nu, D = sys.D;
+  RowCache<T, kNnzB> brow;
+  load_row(brow, sys.b_rp, sys.b_ci, sys.b_v, tid, tid < nx);
+
+  T* sUc = reinterpret_cast<T*>(smem_raw + kRedDoubles * sizeof(double)) +
+           (size_t)kChunk * (D + 2 * nu + nx + 4);
+  T* sXc = sUc + nu;
+  for (int i = tid; i < nx; i += kBlock) sXc[i] = x.affine ? td.p[i] : T(0);
+  for (int j = tid; j < nu; j += kBlock) sUc[j] = T(0);
+  __syncthreads();
+
+  double st0 = 0.0, st1 = 0.0, st2 = 0.0;  // residual / |Hz| / |t| maxima, or power sums
+  // the root path: ancestors of this leaf chain, root first
+  const int p0 = td.path_off[wi.chain], p1 = td.path_off[wi.chain + 1];
+  for (int q = p0; q < p1; ++q) {
+    const int code = td.path[q];
+    const bool own = code < 0;
+    const ChainDesc ac = td.chains[own ? -1 - code : code];
+    fwd_segment<T, NXL>(sys, td, x, mode, ac.first, ac.len, own, smem_raw, brow, st0, st1, st2);
+  }
+  const ChainDesc ch = td.chains[wi.chain];
+  fwd_segment<T, NXL>(sys, td, x, mode, ch.first, ch.len, true, smem_raw, brow, st0, st1, st2);
+
+  // partials of this leaf chain
   if (mode == kModeAPG) {
     st0 = wave_nanmax(st0);
     st1 = wave_nanmax(st1);
@@ -603,47 +692,44 @@ __global__ __launch_bounds__(kBlock) void k_forward(SysDev<T> sys, const TreeDev
   __syncthreads();
   if (tid == 0) {
     double* out = td.cstat + (size_t)wi.chain * kStat;
-    if (mode == kModeAPG) {
-      double a0 = sRed[0], a1 = sRed[1], a2 = sRed[2];
-      for (int w = 1; w < kBlock / 64; ++w) {
+    double a0 = sRed[0], a1 = sRed[1], a2 = sRed[2];
+    for (int w = 1; w < kBlock / 64; ++w) {
+      if (mode == kModeAPG) {
         a0 = nanmax(a0, sRed[3 * w]);
         a1 = nanmax(a1, sRed[3 * w + 1]);
         a2 = nanmax(a2, sRed[3 * w + 2]);
-      }
-      out[0] = a0; out[1] = a1; out[2] = a2; out[3] = 0.0;
-    } else if (mode == kModePower) {
-      double a0 = sRed[0], a1 = sRed[1];
-      for (int w = 1; w < kBlock / 64; ++w) {
+      } else {
         a0 += sRed[3 * w];
         a1 += sRed[3 * w + 1];
       }
-      out[0] = a0; out[1] = a1; out[2] = 0.0; out[3] = 0.0;
     }
+    st_agent(&out[0], a0);
+    st_agent(&out[1], a1);
+    st_agent(&out[2], a2);
+    st_agent(&out[3], 0.0);
   }
-}
+  if (mode == kModeSolve) return;
 
-// ---------------------------------------------------------------------------
-// per-tree end of iteration
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_iter_end(const IterRef* __restrict__ refs, int mode) {
-  const IterRef r = refs[blockIdx.x];
-  TreeState* st = r.st;
-  const int lane = threadIdx.x;
-  const int done0 = st->done;
-  if (done0) {
-    if (lane == 0) r.done_out[r.slot] = 1;
-    return;
+  // the last leaf chain of the tree to finish ends the tree's iteration
+  wait_mem();
+  __syncthreads();
+  if (tid == 0) {
+    const int prev = __hip_atomic_fetch_add(&st->fwd_count, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev == td.n_leaves - 1);
   }
-  const int it = st->iter;
+  __syncthreads();
+  if (!s_last || wave != 0) return;
+  const int it = x.it;
   if (mode == kModeAPG) {
     const bool check = ((it + 1) % st->check_every == 0) || (it + 1 >= st->max_iter);
     int done = 0;
     if (check) {
       double rm = 0.0, hm = 0.0;
-      for (int c = lane; c < r.n_chains; c += 64) {
-        rm = nanmax(rm, r.cstat[(size_t)c * kStat + 0]);
-        hm = nanmax(hm, r.cstat[(size_t)c * kStat + 1]);
-        hm = nanmax(hm, r.cstat[(size_t)c * kStat + 2]);
+      for (int k = lane; k < td.n_leaves; k += 64) {
+        const double* cs = td.cstat + (size_t)td.leaves[k] * kStat;
+        rm = nanmax(rm, ld_agent(&cs[0]));
+        hm = nanmax(hm, ld_agent(&cs[1]));
+        hm = nanmax(hm, ld_agent(&cs[2]));
       }
       rm = wave_nanmax(rm);
       hm = wave_nanmax(hm);
@@ -668,30 +754,27 @@ __global__ __launch_bounds__(64) void k_iter_end(const IterRef* __restrict__ ref
       }
     }
     if (lane == 0) {
+      st_agent(&st->fwd_count, 0);
       st->iter = it + 1;
-      r.done_out[r.slot] = done;
+      done_out[wi.tree] = done;
     }
-  } else if (mode == kModePower) {
+  } else {  // power iteration: Rayleigh quotient and normalisation
     double gg = 0.0, wg = 0.0;
-    for (int c = lane; c < r.n_chains; c += 64) {
-      gg += r.cstat[(size_t)c * kStat + 0];
-      wg += r.cstat[(size_t)c * kStat + 1];
+    for (int k = lane; k < td.n_leaves; k += 64) {
+      const double* cs = td.cstat + (size_t)td.leaves[k] * kStat;
+      gg += ld_agent(&cs[0]);
+      wg += ld_agent(&cs[1]);
     }
     gg = wave_sum(gg);
     wg = wave_sum(wg);
     if (lane == 0) {
       st->lmax_est = wg;
       st->in_scale = gg > 0.0 ? 1.0 / sqrt(gg) : 0.0;
+      st_agent(&st->fwd_count, 0);
       st->iter = it + 1;
-      r.done_out[r.slot] = 0;
+      done_out[wi.tree] = 0;
     }
   }
-}
-
-template <typename T>
-__global__ void k_narrow(const double* __restrict__ src, T* __restrict__ dst, size_t n) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = (T)src[i];
 }
 
 template <typename T>
@@ -700,9 +783,6 @@ __global__ void k_widen(const T* __restrict__ src, double* __restrict__ dst, siz
   if (i < n) dst[i] = (double)src[i];
 }
 
-// ---------------------------------------------------------------------------
-// launchers
-// ---------------------------------------------------------------------------
 // Dynamic LDS above 64 KiB needs an explicit per-kernel opt-in (gfx950 has
 // 160 KiB per CU).
 template <typename K>
@@ -714,6 +794,9 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
                            const double* ctab, int mode, hipStream_t s) {
@@ -735,33 +818,21 @@ hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const 
 
 template <typename T>
 hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
-                          const double* ctab, int mode, hipStream_t s) {
+                          const double* ctab, int mode, int32_t* done_out, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   const size_t lds = lds_bytes_forward(sys.nx, sys.nu, sizeof(T));
   if (sys.nu > 128 || sys.nx > 128) return hipErrorInvalidValue;
   if (sys.nx <= 64) {
     hipError_t e = allow_lds(k_forward<T, 1>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_forward<T, 1>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode);
+    hipLaunchKernelGGL((k_forward<T, 1>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode,
+                       done_out);
   } else {
     hipError_t e = allow_lds(k_forward<T, 2>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_forward<T, 2>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode);
+    hipLaunchKernelGGL((k_forward<T, 2>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode,
+                       done_out);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_iter_end_refs(const void* refs, int n_trees, int mode, hipStream_t s) {
-  if (n_trees <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_iter_end, dim3(n_trees), dim3(64), 0, s, reinterpret_cast<const IterRef*>(refs), mode);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_convert_dual(const double* src, T* dst, size_t n, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(k_narrow<T>, dim3(blocks), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 
@@ -778,10 +849,9 @@ template hipError_t launch_backward<double>(const SysDev<double>&, const TreeDev
 template hipError_t launch_backward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
                                            const double*, int, hipStream_t);
 template hipError_t launch_forward<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
-                                           const double*, int, hipStream_t);
+                                           const double*, int, int32_t*, hipStream_t);
 template hipError_t launch_forward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
-                                          const double*, int, hipStream_t);
-template hipError_t launch_convert_dual<float>(const double*, float*, size_t, hipStream_t);
+                                          const double*, int, int32_t*, hipStream_t);
 template hipError_t launch_widen<float>(const float*, double*, size_t, hipStream_t);
 
 }  // namespace smpc

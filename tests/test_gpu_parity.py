@@ -43,6 +43,7 @@ STEP_CASES = {
     "ragged": lambda: ds.random_small_instance(1, nx=3, nu=6, nd=2, ne=2, N=5, branching=(3, 2), scenarios=5),
     "single-node": lambda: ds.random_small_instance(3, nx=3, nu=4, nd=2, ne=1, N=1, branching=()),
     "one-scenario": lambda: ds.random_small_instance(4, nx=3, nu=4, nd=2, ne=2, N=7, branching=()),
+    "long-inner-chains": lambda: ds.random_small_instance(6, nx=3, nu=5, nd=2, ne=2, N=7, branching=(2, 1, 1, 3)),
     "barcelona-small": lambda: ds.barcelona_instance(N=6, branching=(3, 2)),
     "barcelona-7260": lambda: ds.barcelona_instance(),
 }
@@ -143,9 +144,9 @@ def test_apg_fp64_tiny_500(ctx):
     assert abs(g["r_primal"] - r.r_primal) <= 1e-9 * max(1.0, r.r_primal)
 
 
-@pytest.mark.parametrize("seed", [0, 5])
-def test_apg_fp64_general_system_scaled(ctx, seed):
-    inst = ds.random_small_instance(seed, nx=4, nu=6, nd=3, ne=2, N=5, branching=(3, 2), scenarios=5)
+@pytest.mark.parametrize("seed,branching,scen", [(0, (3, 2), 5), (5, (3, 2), 5), (7, (2, 1, 1, 3), None)])
+def test_apg_fp64_general_system_scaled(ctx, seed, branching, scen):
+    inst = ds.random_small_instance(seed, nx=4, nu=6, nd=3, ne=2, N=6, branching=branching, scenarios=scen)
     g, r, P = _apg_pair(ctx, inst, 300, precond=1)
     assert _rel(g["u"], r.u) <= 1e-9 and _rel(g["x"], r.x) <= 1e-9 and _rel(g["y"], r.y) <= 1e-9
 
