@@ -105,7 +105,8 @@ int smpc_sys_destroy(smpc_sys* sys);   /* SMPC_EINVAL while trees still use it *
  * stage[0] = 0, parent[0] = -1, parent[n] < n, stage[parent[n]] = stage[n]-1,
  * every node at stage < N-1 has a child, prob > 0, prob[0] = 1 and the
  * children of each node sum to its probability (relative 1e-9).
- * Violations give SMPC_EPROB.  Allocates the tree's device buffers.          */
+ * Violations give SMPC_EPROB; M (2 nx + nu) >= 2^31 gives SMPC_EDIM.
+ * Allocates the tree's device buffers.                                      */
 int smpc_tree_create(smpc_sys* sys, int N, int M, const int32_t* stage,
                      const int32_t* parent, const double* prob, smpc_tree** out);
 int smpc_tree_destroy(smpc_tree* tree);

@@ -896,6 +896,10 @@ int smpc_tree_create(smpc_sys* sys, int N, int M, const int32_t* stage, const in
   if (!sys || !stage || !parent || !prob || !out) return set_error(SMPC_EINVAL, "NULL argument");
   *out = nullptr;
   if (N < 1 || M < 1) return set_error(SMPC_EINVAL, "need N >= 1 and M >= 1 (got N=%d, M=%d)", N, M);
+  // kernels index the per-node arrays with 32-bit element offsets
+  if ((int64_t)M * (2 * sys->nx + sys->nu) >= INT32_MAX)
+    return set_error(SMPC_EDIM, "tree too large: M * (2 nx + nu) = %lld must stay below 2^31",
+                     (long long)M * (2 * sys->nx + sys->nu));
   if (stage[0] != 0 || parent[0] != -1) return set_error(SMPC_EPROB, "node 0 must be the root");
   if (!(std::fabs(prob[0] - 1.0) <= 1e-12)) return set_error(SMPC_EPROB, "root probability must be 1");
   std::vector<int> nch(M, 0);
@@ -972,7 +976,8 @@ int smpc_tree_create(smpc_sys* sys, int N, int M, const int32_t* stage, const in
   }
   t->n_levels = H;
   // leaf chains; each inner chain is owned (its prox is done) by its first
-  // leaf descendant; the root path of every leaf chain, root first
+  // leaf descendant; the root path of every leaf chain as internal node
+  // indices, root first (-1 - node where that leaf chain owns the node)
   const int C0 = (int)t->chains.size();
   std::vector<int> first_leaf(C0, -1);
   for (int c = C0 - 1; c >= 0; --c) {
@@ -989,7 +994,10 @@ int smpc_tree_create(smpc_sys* sys, int N, int M, const int32_t* stage, const in
       std::vector<int32_t> anc;
       for (int a = t->chains[c].parent; a >= 0; a = t->chains[a].parent) anc.push_back(a);
       for (auto it = anc.rbegin(); it != anc.rend(); ++it)
-        t->path.push_back(first_leaf[*it] == c ? -1 - *it : *it);
+        for (int k = 0; k < t->chains[*it].len; ++k) {
+          const int32_t node = t->chains[*it].first + k;  // top to bottom
+          t->path.push_back(first_leaf[*it] == c ? -1 - node : node);
+        }
     }
   }
   t->path_off[C0] = (int32_t)t->path.size();

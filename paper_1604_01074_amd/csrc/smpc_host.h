@@ -113,7 +113,7 @@ struct smpc_tree {
   int n_levels = 0;
   std::vector<int32_t> leaves;    // chains that end at a leaf
   std::vector<int32_t> path_off;  // per chain: range in `path`
-  std::vector<int32_t> path;      // ancestors of each leaf chain (root first); -1-id = owned
+  std::vector<int32_t> path;      // ancestor nodes of each leaf chain (root first); -1-node = owned
   // float64 host copies of the per-node data, internal order
   std::vector<double> beta0;  // beta with q = 0 (root term added per solve)
   std::vector<double> uhat, e, pi;

@@ -100,9 +100,10 @@ struct TreeDev {
   TreeState* st;
   int32_t* cnt;             // per chain: children whose backward sweep is done
   const int32_t* leaves;    // the tree's leaf chains (height 0)
-  const int32_t* path_off;  // per chain: range of its ancestor chains in `path`
-  const int32_t* path;      // ancestor chains, root first; < 0 marks an ancestor
-                            // whose prox this leaf chain performs (-1 - id)
+  const int32_t* path_off;  // per chain: range of its ancestor nodes in `path`
+  const int32_t* path;      // ancestor nodes (internal index), root first; < 0
+                            // marks a node whose prox this leaf chain performs
+                            // (-1 - node); every inner node has one such chain
   int32_t n_chains;
   int32_t n_leaves;
   int32_t M;
@@ -123,8 +124,8 @@ template <typename T>
 hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s);
 
 // Row stride of the zero-padded P on the device (and of the staged rho rows).
-int p_stride(int nu);
-size_t lds_bytes_backward(int nx, int nu, size_t elem);
-size_t lds_bytes_forward(int nx, int nu, size_t elem);
+__host__ __device__ int p_stride(int nu);
+__host__ __device__ size_t lds_bytes_backward(int nx, int nu, size_t elem);
+__host__ __device__ size_t lds_bytes_forward(int nx, int nu, size_t elem);
 
 }  // namespace smpc

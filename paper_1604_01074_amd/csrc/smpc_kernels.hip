@@ -30,6 +30,11 @@
 // B and A are applied in sparse form; P is held in registers.
 #include "smpc_internal.h"
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 namespace smpc {
 
 namespace {
@@ -81,30 +86,68 @@ __device__ __forceinline__ void wait_mem() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Dynamic LDS: 32 float64 reduction slots, then T-typed arrays.
-constexpr int kRedDoubles = 32;
 
-// Nodes of one chain processed together (24 in float32, 12 in float64, which
-// keeps a chunk's staging within LDS at several workgroups per CU).  Within a
-// chunk the work is: wide loads, short per-component scans for the
-// recursions, then wide compute.
+// ---------------------------------------------------------------------------
+// Work layout.  A workgroup is four wave64s with fixed roles:
+//
+//   wave 0      state components i = lane + 64 r (r < NXL): Q in the backward
+//               sweep, x and the sigma~ blocks in the forward rollout
+//   wave 1      idle in the backward scans; x and the zeta~ blocks forward
+//   waves 2, 3  input components j = threadIdx.x - 128: rho backward, ut, u
+//               and the psi~ blocks forward
+//
+// A chain is processed in chunks of consecutive nodes.  Each thread keeps its
+// component's values for every node of the chunk in registers, so the
+// recursions along the chain are running sums in registers; LDS only carries
+// what crosses components (Q for B'Q, ut for B ut, rho for the P product).
+// ---------------------------------------------------------------------------
+
+// Nodes per backward chunk: the P product of a chunk is one or two 16-row
+// MFMA tiles.
 template <typename T>
-struct Chunk {
-  static constexpr int value = sizeof(T) == 4 ? 24 : 12;
+struct ChunkLen {
+  static constexpr int value = sizeof(T) == 4 ? 32 : 16;
 };
 
-// Loads per thread and array issued in one staging batch, before any LDS
-// store (halved in float64 to leave registers for the P slice).
+// Nodes per forward chunk (register arrays of this length per thread).
 template <typename T>
-struct Stage {
-  static constexpr int Y = sizeof(T) == 4 ? 12 : 6;
-  static constexpr int U = sizeof(T) == 4 ? 6 : 3;
-  static constexpr int X = sizeof(T) == 4 ? 4 : 2;
+struct FwdChunk {
+  static constexpr int value = sizeof(T) == 4 ? 16 : 8;
 };
 
-// Sparse rows kept in registers: unused slots have weight 0 and index 0.
+// 16x16x4 matrix-core products.  Operand layouts (both precisions): lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; the four accumulator values
+// of lane l are D[row(l, r)][l % 16], r = 0..3.
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// Sparse rows kept in registers: unused slots have weight 0 and index 0;
+// longer rows are read from the CSR arrays.
 constexpr int kNnzBt = 4;  // B' rows: a flow touches few tanks
 constexpr int kNnzB = 8;   // B rows: a tank is touched by few flows
+
+// Nodes whose loads may be in flight together in the backward staging: the
+// scheduler may not hoist later loads above each batch (with P in registers
+// that would spill).
+constexpr int kLoadBatch = 8;
 
 template <typename T, int K>
 struct RowCache {
@@ -127,6 +170,48 @@ __device__ __forceinline__ void load_row(RowCache<T, K>& r, const int32_t* rp, c
     r.c[q] = q < r.n ? ci[r.q0 + q] : 0;
     r.w[q] = q < r.n ? v[r.q0 + q] : T(0);
   }
+}
+
+// DPP moves within rows of 16 lanes (gfx9 encodings).
+constexpr int kDppQuadSwap1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadSwap2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowRor4 = 0x124;
+constexpr int kDppRowRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane; every lane must be
+// active.  Butterflies inside each row of 16 lanes on the DPP path, then the
+// four row sums in a fixed order.
+template <typename T>
+__device__ __forceinline__ T wave_allsum(T v) {
+  v += dpp_mov<kDppQuadSwap1>(v);
+  v += dpp_mov<kDppQuadSwap2>(v);
+  v += dpp_mov<kDppRowRor4>(v);
+  v += dpp_mov<kDppRowRor8>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Per-workgroup view of one iteration of one tree.
@@ -165,24 +250,34 @@ __device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const TreeSta
   return x;
 }
 
-}  // namespace
-
-int p_stride(int nu) { return nu <= 64 ? 64 : 128; }
-
-size_t lds_bytes_backward(int nx, int nu, size_t elem) {
-  // per chunk node: w (D), beta (nu), xi/Q (nx), r/rho (row padded to the P
-  // stride), -1/(2 pi), 3 scales; two carries
-  const size_t ch = elem == 4 ? Chunk<float>::value : Chunk<double>::value;
-  const size_t D = 2 * (size_t)nx + nu;
-  return kRedDoubles * sizeof(double) + elem * (ch * (D + nu + nx + p_stride(nu) + 4) + nx + nu);
+// The dual point the solve step is evaluated at: the extrapolated
+// w = y + c (y - y_prev) (APG), the normalised power-iteration vector, or y.
+template <typename T>
+__device__ __forceinline__ T wpoint(const Iter<T>& x, int mode, size_t k) {
+  const T y = x.ycur[k];
+  if (mode == kModeAPG) return y + x.c * (y - x.yprv[k]);
+  if (mode == kModePower) return x.in_scale * y;
+  return y;
 }
 
-size_t lds_bytes_forward(int nx, int nu, size_t elem) {
-  // per chunk node: w (D), du/ut, uhat (nu each), e/x (nx), pi, 3 scales;
-  // two carries
-  const size_t ch = elem == 4 ? Chunk<float>::value : Chunk<double>::value;
-  const size_t D = 2 * (size_t)nx + nu;
-  return kRedDoubles * sizeof(double) + elem * (ch * (D + 2 * nu + nx + 4) + nx + nu);
+}  // namespace
+
+__host__ __device__ int p_stride(int nu) { return nu <= 64 ? 64 : 128; }
+
+__host__ __device__ size_t lds_bytes_backward(int nx, int nu, size_t elem) {
+  // the two Q parts of the chunk (2 x chunk x padded nx), rho transposed (P-stride
+  // rows of chunk + 1 entries), -1/(2 pi) for two chunks, two Q carries
+  // (general A), the chain-top exchange
+  const size_t ch = elem == 4 ? ChunkLen<float>::value : ChunkLen<double>::value;
+  const size_t xs = nx <= 64 ? 64 : 128;
+  return elem * (2 * ch * xs + (size_t)p_stride(nu) * (ch + 1) + 2 * ch + 3 * (size_t)nx);
+}
+
+__host__ __device__ size_t lds_bytes_forward(int nx, int nu, size_t elem) {
+  // ut of two chunks (2 x chunk x padded nu), scales and pi of two chunks,
+  // the x carries of waves 0 and 1 (general A), 32 float64 reduction slots
+  const size_t ch = elem == 4 ? FwdChunk<float>::value : FwdChunk<double>::value;
+  return elem * (2 * ch * (size_t)p_stride(nu) + 8 * ch + 2 * (size_t)nx) + 32 * sizeof(double);
 }
 
 namespace {
@@ -190,457 +285,562 @@ namespace {
 // ---------------------------------------------------------------------------
 // backward sweep of one chain
 //
-// Per chunk (bottom-up): stage w = y + c (y - y_prev) and beta of the chunk's
-// nodes (consecutive in memory) with batched loads; form xi_n = S(w_sigma +
-// w_zeta) and r_n = beta_n + S w_psi; run Q_n = xi_n + A' Q_below and
-// rho_n = r_n + B' Q_n + rho_below as per-component scans (one thread per
-// component when A = I); then du_n = -P rho_n / (2 pi_n) for the whole chunk
-// with P held in registers: thread (j, h) keeps P[j][h*KH .. h*KH + KH), the
-// S k-parts of a row sit in adjacent lanes and combine with lane shuffles.
+// Per chunk (bottom-up): wave 0 forms xi_n = S(w_sigma + w_zeta) for its
+// state components and runs Q_n = xi_n + A' Q_below (a running sum when
+// A = I) into LDS; waves 2-3 form r_n = beta_n + S w_psi; after a barrier
+// they add B' Q_n and run rho_n = r_n + rho_below into LDS (transposed);
+// after a second barrier all four waves compute du_n = -P rho_n / (2 pi_n) for
+// the chunk as one GEMM on the matrix cores (P, symmetric, is the B operand
+// held in registers: wave w owns columns [16 NT w, 16 NT (w + 1)) of every
+// 4-row K step).
 // ---------------------------------------------------------------------------
-template <typename T, int S, int KH>
-__device__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode, int chain,
-                          unsigned char* smem_raw, const T (&preg)[KH], const RowCache<T, kNnzBt>& bt) {
-  constexpr int kChunk = Chunk<T>::value;
-  constexpr int kStageY = Stage<T>::Y, kStageU = Stage<T>::U;
-  constexpr int KP = S * KH;
-  const int tid = threadIdx.x;
-  const int nx = sys.nx, nu = sys.nu, D = sys.D;
-  const ChainDesc ch = td.chains[chain];
-  const int pj = tid / S;
-  const int ph = tid % S;
-
-  T* sW = reinterpret_cast<T*>(smem_raw + kRedDoubles * sizeof(double));  // kChunk x D
-  T* sB = sW + (size_t)kChunk * D;                                        // kChunk x nu
-  T* sQ = sB + (size_t)kChunk * nu;                                       // kChunk x nx
-  T* sR = sQ + (size_t)kChunk * nx;  // kChunk x KP, entries nu..KP-1 stay zero
-  T* sI = sR + (size_t)kChunk * KP;  // kChunk
-  T* sS = sI + kChunk;               // kChunk x 3
-  T* sQc = sS + 3 * kChunk;
-  T* sRc = sQc + nx;
-
-  // cost-to-go terms handed up by the child chains of the bottom node
-  for (int i = tid; i < nx; i += kBlock) {
-    T acc = T(0);
-    for (int k = 0; k < ch.child_count; ++k) acc += ld_agent(&td.ctopQ[(size_t)(ch.child_begin + k) * nx + i]);
-    sQc[i] = acc;
-  }
-  for (int j = tid; j < nu; j += kBlock) {
-    T acc = T(0);
-    for (int k = 0; k < ch.child_count; ++k) acc += ld_agent(&td.ctopR[(size_t)(ch.child_begin + k) * nu + j]);
-    sRc[j] = acc;
-  }
-  for (int e = tid; e < kChunk * (KP - nu); e += kBlock) {
-    const int cc = e / (KP - nu);
-    sR[cc * KP + nu + (e - cc * (KP - nu))] = T(0);
-  }
-
-  for (int top = ch.len; top > 0; top -= kChunk) {
-    const int k0 = top > kChunk ? top - kChunk : 0;
-    const int C = top - k0;
-    const int nb = ch.first + k0;  // internal index of the chunk's first node
-    {
-      const int ny = C * D;
-      const int nbt = x.affine ? C * nu : 0;
-      const size_t oy = (size_t)nb * D, ob = (size_t)nb * nu;
-      for (int b = 0; b * kStageY * kBlock < ny || b * kStageU * kBlock < nbt; ++b) {
-        T ry[kStageY], rp[kStageY], rb[kStageU];
-        T rs = T(1), rpi = T(1);
-#pragma unroll
-        for (int u = 0; u < kStageY; ++u) {
-          const int e = (b * kStageY + u) * kBlock + tid;
-          ry[u] = e < ny ? x.ycur[oy + e] : T(0);
-          rp[u] = (mode == kModeAPG && e < ny) ? x.yprv[oy + e] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < kStageU; ++u) {
-          const int e = (b * kStageU + u) * kBlock + tid;
-          rb[u] = e < nbt ? td.beta[ob + e] : T(0);
-        }
-        if (b == 0) {
-          if (tid < 3 * C && x.scaled) rs = td.scale[(size_t)nb * 3 + tid];
-          if (tid < C) rpi = td.pi[nb + tid];
-        }
-#pragma unroll
-        for (int u = 0; u < kStageY; ++u) {
-          const int e = (b * kStageY + u) * kBlock + tid;
-          if (e < ny) {
-            const T y = ry[u];
-            sW[e] = mode == kModeAPG ? y + x.c * (y - rp[u]) : (mode == kModePower ? x.in_scale * y : y);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kStageU; ++u) {
-          const int e = (b * kStageU + u) * kBlock + tid;
-          if (e < nbt) sB[e] = rb[u];
-        }
-        if (b == 0) {
-          if (tid < 3 * C) sS[tid] = rs;
-          if (tid < C) sI[tid] = T(-0.5) / rpi;
-        }
-      }
-    }
-    __syncthreads();
-    // xi = S(w_sigma + w_zeta) and r = beta + S w_psi
-    for (int e = tid; e < C * nx; e += kBlock) {
-      const int cc = e / nx;
-      const int i = e - cc * nx;
-      sQ[e] = sS[3 * cc] * sW[cc * D + i] + sS[3 * cc + 1] * sW[cc * D + nx + i];
-    }
-    for (int e = tid; e < C * nu; e += kBlock) {
-      const int cc = e / nu;
-      const int j = e - cc * nu;
-      sR[cc * KP + j] = (x.affine ? sB[e] : T(0)) + sS[3 * cc + 2] * sW[cc * D + 2 * nx + j];
-    }
-    __syncthreads();
-    // Q recursion, bottom node of the chunk first
-    if (sys.a_identity) {
-      if (tid < nx) {
-        T q = sQc[tid];
-        for (int cc = C - 1; cc >= 0; --cc) {
-          q += sQ[cc * nx + tid];
-          sQ[cc * nx + tid] = q;
-        }
-        sQc[tid] = q;
-      }
-    } else {
-      for (int cc = C - 1; cc >= 0; --cc) {
-        if (tid < nx) {
-          T q = sQ[cc * nx + tid];
-          for (int r = sys.at_rp[tid]; r < sys.at_rp[tid + 1]; ++r) q += sys.at_v[r] * sQc[sys.at_ci[r]];
-          sQ[cc * nx + tid] = q;
-        }
-        __syncthreads();
-        if (tid < nx) sQc[tid] = sQ[cc * nx + tid];
-        __syncthreads();
-      }
-    }
-    __syncthreads();
-    // rho recursion (one thread per input component)
-    if (tid < nu) {
-      T r = sRc[tid];
-      for (int cc = C - 1; cc >= 0; --cc) {
-        T g = sR[cc * KP + tid];
-        if (bt.n <= kNnzBt) {
-#pragma unroll
-          for (int q = 0; q < kNnzBt; ++q) g += bt.w[q] * sQ[cc * nx + bt.c[q]];
-        } else {
-          for (int q = bt.q0; q < bt.q1; ++q) g += sys.bt_v[q] * sQ[cc * nx + sys.bt_ci[q]];
-        }
-        r += g;
-        sR[cc * KP + tid] = r;
-      }
-      sRc[tid] = r;
-    }
-    __syncthreads();
-    // du = -P rho / (2 pi): branch-free; padded entries of P and rho are zero,
-    // rows cc >= C are computed from stale finite values and not stored
-    T acc[kChunk];
-#pragma unroll
-    for (int cc = 0; cc < kChunk; ++cc) acc[cc] = T(0);
-#pragma unroll
-    for (int kk = 0; kk < KH; ++kk) {
-      const T pv = preg[kk];
-      const int k = ph * KH + kk;
-#pragma unroll
-      for (int cc = 0; cc < kChunk; ++cc) acc[cc] += pv * sR[cc * KP + k];
-    }
-#pragma unroll
-    for (int cc = 0; cc < kChunk; ++cc) {
-      T v = acc[cc];
-      if (S >= 2) v += __shfl_xor(v, 1, 64);
-      if (S >= 4) v += __shfl_xor(v, 2, 64);
-      acc[cc] = v;
-    }
-    if (ph == 0 && pj < nu) {
-#pragma unroll
-      for (int cc = 0; cc < kChunk; ++cc)
-        if (cc < C) td.du[(size_t)(nb + cc) * nu + pj] = acc[cc] * sI[cc];
-    }
-    __syncthreads();
-  }
-  // top node of the chain: hand Q and rho to the parent chain
-  for (int i = tid; i < nx; i += kBlock) st_agent(&td.ctopQ[(size_t)chain * nx + i], sQc[i]);
-  for (int j = tid; j < nu; j += kBlock) st_agent(&td.ctopR[(size_t)chain * nu + j], sRc[j]);
-}
-
-template <typename T, int S, int KH>
-__global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
-                                                        const WorkItem* __restrict__ items,
-                                                        const double* __restrict__ ctab, int mode) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int s_last;
-  constexpr int KP = S * KH;
-  const int tid = threadIdx.x;
-  const WorkItem wi = items[blockIdx.x];
-  const TreeDev<T>& td = trees[wi.tree];
-  const TreeState* st = td.st;
-  if (st->done) return;
-  const Iter<T> x = make_iter(td, st, ctab, mode);
-  const int nu = sys.nu;
-
-  // P slice of this thread (P is stored zero-padded to KP x KP)
-  T preg[KH];
-  {
-    const int pj = tid / S;
-    const int ph = tid % S;
-#pragma unroll
-    for (int kk = 0; kk < KH; ++kk) preg[kk] = sys.P[(size_t)(ph * KH + kk) * KP + pj];
-  }
-  RowCache<T, kNnzBt> bt;
-  load_row(bt, sys.bt_rp, sys.bt_ci, sys.bt_v, tid, tid < nu);
-
-  int chain = wi.chain;
-  while (true) {
-    bwd_chain<T, S, KH>(sys, td, x, mode, chain, smem_raw, preg, bt);
-    const int parent = td.chains[chain].parent;
-    if (parent < 0) break;  // the root chain is done: the sweep is complete
-    // this chain's top terms are stored: count this child done at the parent
-    wait_mem();
-    __syncthreads();
-    if (tid == 0) {
-      const int pc = td.chains[parent].child_count;
-      const int prev = __hip_atomic_fetch_add(&td.cnt[parent], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_last = (prev == pc - 1);
-      if (s_last) st_agent(&td.cnt[parent], 0);  // ready for the next iteration
-    }
-    __syncthreads();
-    if (!s_last) break;  // a sibling is still running; it will sweep the parent
-    chain = parent;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// forward rollout and prox of consecutive nodes [first, first + len)
-//
-// The carries sXc / sUc hold the state x and input increment ut of the node
-// above.  With do_prox the nodes' prox, dual update and primal output are
-// computed; otherwise only the recursion runs (an ancestor another leaf chain
-// owns).  Per chunk: stage w, du, uhat, e (consecutive nodes: contiguous
-// ranges) with batched loads, run ut_n = ut_above + du_n and
-// x_n = A x_above + B ut_n + e_n as per-component scans, then the prox: each
-// (node, sigma|zeta) block is one wave with its Euclidean norm reduced by lane
-// shuffles, the psi entries are spread over all threads.
-// ---------------------------------------------------------------------------
-template <typename T, int NXL>
-__device__ void fwd_segment(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode, int first,
-                            int len, bool do_prox, unsigned char* smem_raw, const RowCache<T, kNnzB>& brow,
-                            double& st0, double& st1, double& st2) {
-  constexpr int kChunk = Chunk<T>::value;
-  constexpr int kStageY = Stage<T>::Y, kStageU = Stage<T>::U, kStageX = Stage<T>::X;
-  constexpr int kWaves = kBlock / 64;
+template <typename T, int KP, int NXL>
+__device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode, int chain,
+                          unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
+                          const RowCache<T, kNnzBt>& bt, int& par) {
+  constexpr int CH = ChunkLen<T>::value;
+  constexpr int RS = CH + 1;  // row stride of the transposed rho (bank spread)
+  constexpr int NT = KP / 64, KS = KP / 4, MT = CH / 16;
+  constexpr int XS = 64 * NXL;  // row stride of the Q parts (>= nx, a constant)
+  typedef typename Mfma<T>::v4 v4;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int nx = sys.nx, nu = sys.nu, D = sys.D;
-  const int W = nx + nu;
-  const T cSx = (T)sys.W_x;
-  const T gam_d = (T)sys.gamma_d;
-  const bool prox = do_prox && mode != kModeSolve;
+  const int j = tid - 128;
+  const bool ju = wave >= 2 && j < nu;
+  const ChainDesc ch = td.chains[chain];
 
-  T* sW = reinterpret_cast<T*>(smem_raw + kRedDoubles * sizeof(double));  // kChunk x D
-  T* sU = sW + (size_t)kChunk * D;                                        // kChunk x nu
-  T* sH = sU + (size_t)kChunk * nu;                                       // kChunk x nu (uhat)
-  T* sX = sH + (size_t)kChunk * nu;                                       // kChunk x nx
-  T* sPi = sX + (size_t)kChunk * nx;                                      // kChunk
-  T* sS = sPi + kChunk;                                                   // kChunk x 3
-  T* sUc = sS + 3 * kChunk;
-  T* sXc = sUc + nu;
+  T* sQ = reinterpret_cast<T*>(smem_raw);  // 2 x CH x XS: Q parts of waves 0, 1
+  T* sRt = sQ + 2 * CH * XS;               // KP x RS: sRt[j * RS + cc]; rows nu..KP-1 zero
+  T* sI = sRt + (size_t)KP * RS;           // 2 x CH
+  T* sQc = sI + 2 * CH;                    // 2 x nx: carries (general A)
+  T* sTop = sQc + 2 * nx;                  // nx: wave 1's carry at the chain top
 
-  for (int k0 = 0; k0 < len; k0 += kChunk) {
-    const int C = len - k0 < kChunk ? len - k0 : kChunk;
-    const int nb = first + k0;
-    {
-      const int ny = prox ? C * D : 0;
-      const int nuu = C * nu;
-      const int nh = (x.affine && do_prox) ? C * nu : 0;
-      const int ne = x.affine ? C * nx : 0;
-      const size_t oy = (size_t)nb * D, ou = (size_t)nb * nu, ox = (size_t)nb * nx;
-      for (int b = 0; b * kStageY * kBlock < ny || b * kStageU * kBlock < nuu || b * kStageX * kBlock < C * nx;
-           ++b) {
-        T ry[kStageY], rp[kStageY], ru[kStageU], rh[kStageU], rx[kStageX];
-        T rs = T(1), rpi = T(1);
+  // Q is linear in xi = S_sigma w_sigma + S_zeta w_zeta: wave 0 runs the
+  // recursion on the sigma~ part plus the children's terms, wave 1 on the
+  // zeta~ part; B' Q reads both.  Cost-to-go terms handed up by the child
+  // chains: all loads of a batch are issued before the (ordered) sum.
+  const int nch = ch.child_count;
+  T qc[NXL], rc = T(0);
 #pragma unroll
-        for (int u = 0; u < kStageY; ++u) {
-          const int e = (b * kStageY + u) * kBlock + tid;
-          ry[u] = e < ny ? x.ycur[oy + e] : T(0);
-          rp[u] = (mode == kModeAPG && e < ny) ? x.yprv[oy + e] : T(0);
-        }
+  for (int r = 0; r < NXL; ++r) qc[r] = T(0);
+  if (wave == 0) {
 #pragma unroll
-        for (int u = 0; u < kStageU; ++u) {
-          const int e = (b * kStageU + u) * kBlock + tid;
-          ru[u] = e < nuu ? td.du[ou + e] : T(0);
-          rh[u] = e < nh ? td.uhat[ou + e] : T(0);
-        }
+    for (int r = 0; r < NXL; ++r) {
+      const int i = lane + 64 * r;
+      if (i < nx) {
+        for (int k0 = 0; k0 < nch; k0 += 8) {
+          T v[8];
 #pragma unroll
-        for (int u = 0; u < kStageX; ++u) {
-          const int e = (b * kStageX + u) * kBlock + tid;
-          rx[u] = e < ne ? td.e[ox + e] : T(0);
-        }
-        if (b == 0 && prox) {
-          if (tid < 3 * C && x.scaled) rs = td.scale[(size_t)nb * 3 + tid];
-          if (tid < C) rpi = td.pi[nb + tid];
-        }
+          for (int k = 0; k < 8; ++k)
+            v[k] = k0 + k < nch ? ld_agent(&td.ctopQ[(size_t)(ch.child_begin + k0 + k) * nx + i]) : T(0);
 #pragma unroll
-        for (int u = 0; u < kStageY; ++u) {
-          const int e = (b * kStageY + u) * kBlock + tid;
-          if (e < ny) {
-            const T y = ry[u];
-            sW[e] = mode == kModeAPG ? y + x.c * (y - rp[u]) : x.in_scale * y;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kStageU; ++u) {
-          const int e = (b * kStageU + u) * kBlock + tid;
-          if (e < nuu) {
-            sU[e] = ru[u];
-            sH[e] = rh[u];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kStageX; ++u) {
-          const int e = (b * kStageX + u) * kBlock + tid;
-          if (e < C * nx) sX[e] = rx[u];
-        }
-        if (b == 0) {
-          if (tid < 3 * C) sS[tid] = rs;
-          if (tid < C) sPi[tid] = rpi;
+          for (int k = 0; k < 8; ++k)
+            if (k0 + k < nch) qc[r] += v[k];
         }
       }
     }
-    __syncthreads();
-    // ut recursion (top node of the chunk first)
-    if (tid < nu) {
-      T u = sUc[tid];
-      for (int cc = 0; cc < C; ++cc) {
-        u += sU[cc * nu + tid];
-        sU[cc * nu + tid] = u;
-      }
-      sUc[tid] = u;
-    }
-    __syncthreads();
-    // x recursion
-    if (sys.a_identity) {
-      if (tid < nx) {
-        T xv = sXc[tid];
-        for (int cc = 0; cc < C; ++cc) {
-          T g = sX[cc * nx + tid];
-          if (brow.n <= kNnzB) {
+  } else if (ju) {
+    for (int k0 = 0; k0 < nch; k0 += 8) {
+      T v[8];
 #pragma unroll
-            for (int r = 0; r < kNnzB; ++r) g += brow.w[r] * sU[cc * nu + brow.c[r]];
-          } else {
-            for (int r = brow.q0; r < brow.q1; ++r) g += sys.b_v[r] * sU[cc * nu + sys.b_ci[r]];
-          }
-          xv += g;
-          sX[cc * nx + tid] = xv;
-        }
-        sXc[tid] = xv;
-      }
-    } else {
-      for (int cc = 0; cc < C; ++cc) {
-        if (tid < nx) {
-          T xv = sX[cc * nx + tid];
-          for (int r = sys.a_rp[tid]; r < sys.a_rp[tid + 1]; ++r) xv += sys.a_v[r] * sXc[sys.a_ci[r]];
-          for (int r = sys.b_rp[tid]; r < sys.b_rp[tid + 1]; ++r) xv += sys.b_v[r] * sU[cc * nu + sys.b_ci[r]];
-          sX[cc * nx + tid] = xv;
-        }
-        __syncthreads();
-        if (tid < nx) sXc[tid] = sX[cc * nx + tid];
-        __syncthreads();
-      }
+      for (int k = 0; k < 8; ++k)
+        v[k] = k0 + k < nch ? ld_agent(&td.ctopR[(size_t)(ch.child_begin + k0 + k) * nu + j]) : T(0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k0 + k < nch) rc += v[k];
     }
-    __syncthreads();
+  }
 
-    if (do_prox) {
-      // distance blocks: one wave per (node, block)
-      for (int p = wave; p < 2 * C; p += kWaves) {  // wave-uniform loop
-        const int cc = p >> 1;
-        const int b = p & 1;
-        const size_t n = (size_t)(nb + cc);
-        const T s = sS[3 * cc + b];
-        T a_[NXL], pa_[NXL], hz_[NXL];
-        T dsq = T(0);
+  for (int top = ch.len; top > 0; top -= CH) {
+    const int k0 = top > CH ? top - CH : 0;
+    const int C = top - k0;
+    const int nb = ch.first + k0;  // internal index of the chunk's first node
+    T* sIp = sI + par * CH;
+    if (tid < C) sIp[tid] = T(-0.5) / td.pi[nb + tid];
+    if (wave < 2) {
+      // this wave's part of xi_n (block b = wave); with A = I the Q recursion
+      // runs along, bottom node first
+      const int b = wave;
+      T* sQw = sQ + wave * CH * XS;
 #pragma unroll
-        for (int r = 0; r < NXL; ++r) {
-          const int i = lane + 64 * r;
-          a_[r] = pa_[r] = hz_[r] = T(0);
-          if (i < nx) {
-            const T hzv = sX[cc * nx + i];
-            hz_[r] = hzv;
-            if (x.write_z && b == 0) td.z[n * W + i] = hzv;
-            if (mode == kModePower) {
-              const T g = -s * hzv;
-              x.ynew[n * D + b * nx + i] = g;
-              st0 += (double)g * (double)g;
-              st1 += (double)sW[cc * D + b * nx + i] * (double)g;
-            } else if (mode == kModeAPG) {
-              const T w = sW[cc * D + b * nx + i];
-              const T a = (w * x.ilam + s * hzv) / s;
-              const T pa = b == 0 ? (a > sys.xs[i] ? a : sys.xs[i]) : clampv(a, sys.xmin[i], sys.xmax[i]);
-              const T dd = a - pa;
-              dsq += dd * dd;
-              a_[r] = a;
-              pa_[r] = pa;
+      for (int r = 0; r < NXL; ++r) {
+        const int i = lane + 64 * r;
+#pragma unroll
+        for (int cc = CH - 1; cc >= 0; --cc) {
+          if (cc < C && i < nx) {
+            const size_t n = (size_t)(nb + cc);
+            const T sb = x.scaled ? td.scale[n * 3 + b] : T(1);
+            const T xi = sb * wpoint(x, mode, n * D + b * nx + i);
+            if (sys.a_identity) {
+              qc[r] += xi;
+              sQw[cc * XS + i] = qc[r];
+            } else {
+              sQw[cc * XS + i] = xi;
+            }
+          }
+          if (cc % kLoadBatch == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      if (!sys.a_identity) {
+        // Q_n = xi_n + A' Q_below one node at a time; the carry is exchanged
+        // through LDS within this wave
+        T* cq = sQc + (size_t)wave * nx;
+#pragma unroll
+        for (int r = 0; r < NXL; ++r)
+          if (lane + 64 * r < nx) cq[lane + 64 * r] = qc[r];
+        for (int cc = C - 1; cc >= 0; --cc) {
+          __builtin_amdgcn_wave_barrier();
+          T q[NXL];
+#pragma unroll
+          for (int r = 0; r < NXL; ++r) {
+            const int i = lane + 64 * r;
+            q[r] = T(0);
+            if (i < nx) {
+              q[r] = sQw[cc * XS + i];
+              for (int k = sys.at_rp[i]; k < sys.at_rp[i + 1]; ++k) q[r] += sys.at_v[k] * cq[sys.at_ci[k]];
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+#pragma unroll
+          for (int r = 0; r < NXL; ++r) {
+            const int i = lane + 64 * r;
+            if (i < nx) {
+              sQw[cc * XS + i] = q[r];
+              cq[i] = q[r];
+              qc[r] = q[r];
             }
           }
         }
-        if (mode != kModeAPG) continue;
-        dsq = wave_sum(dsq);
-        const T del = sqrt(dsq);
-        const T cb = b == 0 ? (sys.safety_by_prob ? cSx * sPi[cc] : cSx) : gam_d;
-        const T tau = cb * x.ilam / (s * s);
-#pragma unroll
-        for (int r = 0; r < NXL; ++r) {
-          const int i = lane + 64 * r;
-          if (i < nx) {
-            const T a = a_[r], pa = pa_[r];
-            const T tun = del <= tau ? pa : a - (tau / del) * (a - pa);
-            const T hzv = hz_[r];
-            x.ynew[n * D + b * nx + i] = sW[cc * D + b * nx + i] + x.lam * (s * hzv - s * tun);
-            st0 = nanmax(st0, fabs((double)hzv - (double)tun));
-            st1 = nanmax(st1, fabs((double)hzv));
-            st2 = nanmax(st2, fabs((double)tun));
-          }
-        }
-      }
-      // psi blocks: input box
-      for (int e = tid; e < C * nu; e += kBlock) {
-        const int cc = e / nu;
-        const int j = e - cc * nu;
-        const size_t n = (size_t)(nb + cc);
-        const T u = sU[cc * nu + j] + sH[cc * nu + j];
-        if (x.write_z) td.z[n * W + nx + j] = u;
-        if (mode == kModeSolve) continue;
-        const T s = sS[3 * cc + 2];
-        const T w = sW[cc * D + 2 * nx + j];
-        if (mode == kModePower) {
-          const T g = -s * u;
-          x.ynew[n * D + 2 * nx + j] = g;
-          st0 += (double)g * (double)g;
-          st1 += (double)w * (double)g;
-          continue;
-        }
-        const T a = (w * x.ilam + s * u) / s;
-        const T tun = clampv(a, sys.umin[j], sys.umax[j]);
-        x.ynew[n * D + 2 * nx + j] = w + x.lam * (s * u - s * tun);
-        st0 = nanmax(st0, fabs((double)u - (double)tun));
-        st1 = nanmax(st1, fabs((double)u));
-        st2 = nanmax(st2, fabs((double)tun));
       }
     }
-    __syncthreads();
+    if (ju) {
+      // r_n = beta_n + S w_psi, parked in this thread's row of the rho tile
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc)
+        if (cc < C) {
+          const size_t n = (size_t)(nb + cc);
+          const T s2 = x.scaled ? td.scale[n * 3 + 2] : T(1);
+          sRt[j * RS + cc] = (x.affine ? td.beta[n * nu + j] : T(0)) + s2 * wpoint(x, mode, n * D + 2 * nx + j);
+        }
+    }
+    __syncthreads();  // Q parts complete
+    if (ju) {
+      // rho recursion, bottom node first: r_n + B' Q_n + rho_below
+      const T* sQz = sQ + CH * XS;
+#pragma unroll
+      for (int cc = CH - 1; cc >= 0; --cc)
+        if (cc < C) {
+          T g = sRt[j * RS + cc];
+          if (bt.n <= kNnzBt) {
+#pragma unroll
+            for (int q = 0; q < kNnzBt; ++q) g += bt.w[q] * (sQ[cc * XS + bt.c[q]] + sQz[cc * XS + bt.c[q]]);
+          } else {
+            for (int q = bt.q0; q < bt.q1; ++q)
+              g += sys.bt_v[q] * (sQ[cc * XS + sys.bt_ci[q]] + sQz[cc * XS + sys.bt_ci[q]]);
+          }
+          rc += g;
+          sRt[j * RS + cc] = rc;
+          if (cc % kLoadBatch == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    __syncthreads();  // sRt complete
+    // du = -P rho / (2 pi) on the matrix cores.  Rows cc >= C of the rho tile
+    // hold stale values: they only reach output rows that are not stored.
+    v4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[m][t] = v4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      T a[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) a[m] = sRt[(4 * st + (lane >> 4)) * RS + 16 * m + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) acc[m][t] = Mfma<T>::op(a[m], preg[st * NT + t], acc[m][t]);
+      if (st % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int jj = 16 * (wave * NT + t) + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int cc = 16 * m + Mfma<T>::row(lane, r);
+          if (cc < C && jj < nu) td.du[(size_t)(nb + cc) * nu + jj] = acc[m][t][r] * sIp[cc];
+        }
+      }
+    par ^= 1;
+  }
+  // top node of the chain: hand Q (both parts) and rho to the parent chain
+  if (wave == 1) {
+#pragma unroll
+    for (int r = 0; r < NXL; ++r)
+      if (lane + 64 * r < nx) sTop[lane + 64 * r] = qc[r];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int r = 0; r < NXL; ++r)
+      if (lane + 64 * r < nx)
+        st_agent(&td.ctopQ[(size_t)chain * nx + lane + 64 * r], qc[r] + sTop[lane + 64 * r]);
+  } else if (ju) {
+    st_agent(&td.ctopR[(size_t)chain * nu + j], rc);
   }
 }
 
-template <typename T, int NXL>
+// Persistent: workgroup b takes leaf chains b, b + gridDim.x, ... (longest
+// first), so the register-resident P is loaded once per workgroup.
+template <typename T, int KP, int NXL>
+__global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
+                                                        const WorkItem* __restrict__ items, int n_items,
+                                                        const double* __restrict__ ctab, int mode) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_last;
+  constexpr int CH = ChunkLen<T>::value;
+  constexpr int NT = KP / 64, KS = KP / 4;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nx = sys.nx, nu = sys.nu;
+
+  // this lane's P entries: P[4 st + lane / 16][16 (wave NT + t) + lane % 16]
+  T preg[KS * NT];
+#pragma unroll
+  for (int st = 0; st < KS; ++st)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      preg[st * NT + t] = sys.P[(size_t)(4 * st + (lane >> 4)) * KP + 16 * (wave * NT + t) + (lane & 15)];
+  RowCache<T, kNnzBt> bt;
+  load_row(bt, sys.bt_rp, sys.bt_ci, sys.bt_v, tid - 128, wave >= 2 && tid - 128 < nu);
+  {
+    // padded rows of the transposed rho tile must be finite (they meet the
+    // zero rows of P); nothing else writes them
+    T* sRt = reinterpret_cast<T*>(smem_raw) + 2 * CH * 64 * NXL;
+    for (int e = tid; e < (KP - nu) * (CH + 1); e += kBlock) sRt[(size_t)nu * (CH + 1) + e] = T(0);
+  }
+  int par = 0;
+
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const WorkItem wi = items[item];
+    const TreeDev<T>& td = trees[wi.tree];
+    const TreeState* st = td.st;
+    if (st->done) continue;
+    const Iter<T> x = make_iter(td, st, ctab, mode);
+    int chain = wi.chain;
+    while (true) {
+      bwd_chain<T, KP, NXL>(sys, td, x, mode, chain, smem_raw, preg, bt, par);
+      const int parent = td.chains[chain].parent;
+      if (parent < 0) break;  // the root chain is done: the sweep is complete
+      // this chain's top terms are stored: count this child done at the parent
+      wait_mem();
+      __syncthreads();
+      if (tid == 0) {
+        const int pc = td.chains[parent].child_count;
+        const int prev = __hip_atomic_fetch_add(&td.cnt[parent], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == pc - 1);
+        if (s_last) st_agent(&td.cnt[parent], 0);  // ready for the next iteration
+      }
+      __syncthreads();
+      if (!s_last) break;  // a sibling is still running; it will sweep the parent
+      chain = parent;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward rollout and prox of a list of nodes, each the child of the one
+// before it
+//
+// `codes` lists internal node indices (-1 - node: this workgroup owns the
+// node); nullptr means the owned nodes [first, first + len).  For owned nodes
+// the prox, dual update and primal output are computed; the others only pass
+// the recursion on (ancestors another leaf chain owns).  Per chunk: waves 2-3
+// run ut_n = ut_above + du_n in registers, publish ut in LDS and finish the
+// psi~ blocks; after one barrier waves 0 and 1 both run
+// x_n = A x_above + B ut_n + e_n (a running sum when A = I) and apply the
+// distance prox to the sigma~ (wave 0) and zeta~ (wave 1) blocks, each block
+// norm one wave reduction.
+// ---------------------------------------------------------------------------
+struct Partials {
+  double s0, s1, s2;  // residual / |Hz| / |t| maxima, or power-iteration sums
+};
+
+__device__ __forceinline__ void fold_max(Partials& p, double hz, double t) {
+  p.s0 = nanmax(p.s0, fabs(hz - t));
+  p.s1 = nanmax(p.s1, fabs(hz));
+  p.s2 = nanmax(p.s2, fabs(t));
+}
+
+// The extrapolated dual point from explicit arrays (see wpoint).
+template <typename T>
+__device__ __forceinline__ T wpoint2(int mode, T c, T in_scale, const T* __restrict__ yc, const T* __restrict__ yp,
+                                     size_t k) {
+  const T y = yc[k];
+  if (mode == kModeAPG) return y + c * (y - yp[k]);
+  if (mode == kModePower) return in_scale * y;
+  return y;
+}
+
+// Entry k of a leaf chain's forward sequence: the plen root-path codes, then
+// the chain's own nodes from `first` (owned: -1 - node).
+__device__ __forceinline__ int32_t node_code(const int32_t* __restrict__ codes, int plen, int first, int k) {
+  return k < plen ? codes[k] : -1 - (first + k - plen);
+}
+
+// Waves 2-3, one chunk: ut_n = ut_above + du_n, u = ut + uhat, the input box
+// of the psi~ blocks and the dual update.  The arrays are distinct
+// allocations (the three dual slots rotate), so the loads of later nodes may
+// be issued before the stores of earlier ones.
+template <typename T, int UP>
+__device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const int32_t* __restrict__ codes,
+                                              int plen, int first, int k0, int C, int j, int nx, int nu, int D,
+                                              const T* __restrict__ du, const T* __restrict__ uhat,
+                                              const T* __restrict__ yc, const T* __restrict__ yp,
+                                              const T* __restrict__ scale, T* __restrict__ ynew,
+                                              T* __restrict__ z, T* sUp, T& utc, T ulo, T uhi, Partials& pt) {
+  constexpr int CH = FwdChunk<T>::value;
+  constexpr int US = UP;
+  const int W = nx + nu;
+  // all loads of the chunk first (unconditionally, so that they are in
+  // flight together), then the recursion, the prox and the stores
+  T duv[CH], uhv[CH], wv[CH], sv[CH];
+#pragma unroll
+  for (int cc = 0; cc < CH; ++cc) {
+    duv[cc] = uhv[cc] = wv[cc] = T(0);
+    sv[cc] = T(1);
+    if (cc < C) {
+      const int32_t code = node_code(codes, plen, first, k0 + cc);
+      const size_t n = (size_t)(code < 0 ? -1 - code : code);
+      duv[cc] = du[n * nu + j];
+      if (x.affine) uhv[cc] = uhat[n * nu + j];
+      if (mode != kModeSolve) {
+        wv[cc] = wpoint2(mode, x.c, x.in_scale, yc, yp, n * D + 2 * nx + j);
+        if (x.scaled) sv[cc] = scale[n * 3 + 2];
+      }
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < CH; ++cc)
+    if (cc < C) {
+      const int32_t code = node_code(codes, plen, first, k0 + cc);
+      const bool own = code < 0;
+      const size_t n = (size_t)(own ? -1 - code : code);
+      utc += duv[cc];
+      sUp[cc * US + j] = utc;
+      if (own) {
+        const T u = utc + uhv[cc];
+        if (x.write_z) z[n * W + nx + j] = u;
+        if (mode != kModeSolve) {
+          const T s = sv[cc];
+          const T w = wv[cc];
+          if (mode == kModePower) {
+            const T g = -s * u;
+            ynew[n * D + 2 * nx + j] = g;
+            pt.s0 += (double)g * (double)g;
+            pt.s1 += (double)w * (double)g;
+          } else {
+            const T a = u + w * (x.ilam / s);  // (w / lambda + s u) / s
+            const T t = clampv(a, ulo, uhi);
+            ynew[n * D + 2 * nx + j] = w + x.lam * s * (u - t);
+            fold_max(pt, (double)u, (double)t);
+          }
+        }
+      }
+    }
+}
+
+// Waves 0 (b = 0, sigma~) and 1 (b = 1, zeta~), one chunk after ut is
+// published: x_n = A x_above + B ut_n + e_n node by node, then the distance
+// prox of block b of owned nodes (the block norm is one wave reduction) and
+// the dual update.
+template <typename T, int NXL, int UP>
+__device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T>& x, int b,
+                                                const int32_t* __restrict__ codes, int plen, int first, int k0,
+                                                int C,
+                                                const T (&ev)[NXL][FwdChunk<T>::value],
+                                                const T (&wv)[NXL][FwdChunk<T>::value],
+                                                const RowCache<T, kNnzB> (&brow)[NXL], const T (&bnd)[NXL][2],
+                                                const T* sSP, T* __restrict__ ynew, T* __restrict__ z,
+                                                const T* sUp, T* cx, T (&xc)[NXL], Partials& pt) {
+  constexpr int CH = FwdChunk<T>::value;
+  constexpr int US = UP;
+  const int lane = threadIdx.x & 63;
+  const int nx = sys.nx, nu = sys.nu, D = sys.D;
+  const int W = nx + nu;
+  if (!sys.a_identity) {
+#pragma unroll
+    for (int r = 0; r < NXL; ++r)
+      if (lane + 64 * r < nx) cx[lane + 64 * r] = xc[r];
+  }
+#pragma unroll
+  for (int cc = 0; cc < CH; ++cc) {
+    if (cc >= C) continue;  // wave-uniform
+    T xn[NXL];
+    if (sys.a_identity) {
+#pragma unroll
+      for (int r = 0; r < NXL; ++r) {
+        const int i = lane + 64 * r;
+        xn[r] = T(0);
+        if (i < nx) {
+          T g = ev[r][cc];
+          if (brow[r].n <= kNnzB) {
+#pragma unroll
+            for (int q = 0; q < kNnzB; ++q) g += brow[r].w[q] * sUp[cc * US + brow[r].c[q]];
+          } else {
+            for (int q = brow[r].q0; q < brow[r].q1; ++q) g += sys.b_v[q] * sUp[cc * US + sys.b_ci[q]];
+          }
+          xc[r] += g;
+          xn[r] = xc[r];
+        }
+      }
+    } else {
+      // one node at a time; the carry is exchanged through LDS within this
+      // wave
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int r = 0; r < NXL; ++r) {
+        const int i = lane + 64 * r;
+        xn[r] = T(0);
+        if (i < nx) {
+          T g = ev[r][cc];
+          for (int q = sys.a_rp[i]; q < sys.a_rp[i + 1]; ++q) g += sys.a_v[q] * cx[sys.a_ci[q]];
+          for (int q = sys.b_rp[i]; q < sys.b_rp[i + 1]; ++q) g += sys.b_v[q] * sUp[cc * US + sys.b_ci[q]];
+          xn[r] = g;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int r = 0; r < NXL; ++r) {
+        const int i = lane + 64 * r;
+        if (i < nx) {
+          cx[i] = xn[r];
+          xc[r] = xn[r];
+        }
+      }
+    }
+    const int32_t code = node_code(codes, plen, first, k0 + cc);
+    if (code >= 0) continue;  // wave-uniform: the node is owned elsewhere
+    const size_t n = (size_t)(-1 - code);
+    if (x.write_z && b == 0) {
+#pragma unroll
+      for (int r = 0; r < NXL; ++r)
+        if (lane + 64 * r < nx) z[n * W + lane + 64 * r] = xn[r];
+    }
+    if (mode == kModeSolve) continue;
+    const T s = sSP[4 * cc + b];
+    if (mode == kModePower) {
+#pragma unroll
+      for (int r = 0; r < NXL; ++r) {
+        const int i = lane + 64 * r;
+        if (i < nx) {
+          const T g = -s * xn[r];
+          ynew[n * D + b * nx + i] = g;
+          pt.s0 += (double)g * (double)g;
+          pt.s1 += (double)wv[r][cc] * (double)g;
+        }
+      }
+      continue;
+    }
+    const T f = x.ilam / s;
+    T a[NXL], pa[NXL];
+    T dsq = T(0);
+#pragma unroll
+    for (int r = 0; r < NXL; ++r) {
+      a[r] = xn[r] + wv[r][cc] * f;  // (w / lambda + s Hz) / s
+      pa[r] = b == 0 ? (a[r] > bnd[r][0] ? a[r] : bnd[r][0]) : clampv(a[r], bnd[r][0], bnd[r][1]);
+      const T d = lane + 64 * r < nx ? a[r] - pa[r] : T(0);
+      dsq += d * d;
+    }
+    const T del = sqrt(wave_allsum(dsq));
+    const T pin = b == 0 && sys.safety_by_prob ? sSP[4 * cc + 3] : T(1);
+    const T cb = b == 0 ? (T)sys.W_x * pin : (T)sys.gamma_d;
+    const T tau = cb * x.ilam / (s * s);
+    const T k = del <= tau ? T(1) : tau / del;
+#pragma unroll
+    for (int r = 0; r < NXL; ++r) {
+      const int i = lane + 64 * r;
+      if (i < nx) {
+        const T t = del <= tau ? pa[r] : a[r] - k * (a[r] - pa[r]);
+        ynew[n * D + b * nx + i] = wv[r][cc] + x.lam * s * (xn[r] - t);
+        fold_max(pt, (double)xn[r], (double)t);
+      }
+    }
+  }
+}
+
+template <typename T, int NXL, int UP>
+__device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode,
+                          const int32_t* codes, int plen, int first, int len, unsigned char* smem_raw,
+                          const RowCache<T, kNnzB> (&brow)[NXL], T (&xc)[NXL], T& utc, const T (&bnd)[NXL][2],
+                          const T (&ubnd)[2], int& par, Partials& pt) {
+  constexpr int CH = FwdChunk<T>::value;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nx = sys.nx, nu = sys.nu, D = sys.D;
+  const int j = tid - 128;
+  const bool ju = wave >= 2 && j < nu;
+  T* sU = reinterpret_cast<T*>(smem_raw);  // 2 x CH x UP (UP >= nu, a constant)
+  T* sSP = sU + 2 * CH * UP;               // 2 x CH x 4: scales and pi of the chunk's nodes
+  T* sXc = sSP + 2 * 4 * CH;               // 2 x nx (general A: carries of waves 0, 1)
+
+  for (int k0 = 0; k0 < len; k0 += CH) {
+    const int C = len - k0 < CH ? len - k0 : CH;
+    T* sUp = sU + par * CH * UP;
+    T* sSPp = sSP + par * 4 * CH;
+    if (tid < C) {
+      const int32_t code = node_code(codes, plen, first, k0 + tid);
+      const size_t n = (size_t)(code < 0 ? -1 - code : code);
+      sSPp[4 * tid] = x.scaled ? td.scale[n * 3] : T(1);
+      sSPp[4 * tid + 1] = x.scaled ? td.scale[n * 3 + 1] : T(1);
+      sSPp[4 * tid + 3] = td.pi[n];
+    }
+    if (ju)
+      fwd_psi_chunk<T, UP>(mode, x, codes, plen, first, k0, C, j, nx, nu, D, td.du, td.uhat, x.ycur, x.yprv, td.scale,
+                       x.ynew, td.z, sUp, utc, ubnd[0], ubnd[1], pt);
+    // waves 0, 1: e and the dual point of the wave's block, loaded before the
+    // barrier
+    const int b = wave;  // 0: sigma~, 1: zeta~
+    T wv[NXL][CH], ev[NXL][CH];
+    if (wave < 2) {
+#pragma unroll
+      for (int r = 0; r < NXL; ++r) {
+        const int i = lane + 64 * r;
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          wv[r][cc] = T(0);
+          ev[r][cc] = T(0);
+          if (cc < C && i < nx) {
+            const int32_t code = node_code(codes, plen, first, k0 + cc);
+            const bool own = code < 0;
+            const size_t n = (size_t)(own ? -1 - code : code);
+            if (x.affine) ev[r][cc] = td.e[n * nx + i];
+            if (own && mode != kModeSolve) wv[r][cc] = wpoint(x, mode, n * D + b * nx + i);
+          }
+        }
+      }
+    }
+    __syncthreads();  // ut of the chunk published
+    if (wave < 2)
+      fwd_state_chunk<T, NXL, UP>(sys, mode, x, b, codes, plen, first, k0, C, ev, wv, brow, bnd, sSPp, x.ynew, td.z, sUp,
+                                  sXc + (size_t)wave * nx, xc, pt);
+    par ^= 1;
+  }
+}
+
+template <typename T, int NXL, int UP>
 __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
                                                        const WorkItem* __restrict__ items,
                                                        const double* __restrict__ ctab, int mode,
                                                        int32_t* __restrict__ done_out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_last;
-  double* sRed = reinterpret_cast<double*>(smem_raw);
-  constexpr int kChunk = Chunk<T>::value;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -652,42 +852,51 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
     return;
   }
   const Iter<T> x = make_iter(td, st, ctab, mode);
-  const int nx = sys.nx, nu = sys.nu, D = sys.D;
-  RowCache<T, kNnzB> brow;
-  load_row(brow, sys.b_rp, sys.b_ci, sys.b_v, tid, tid < nx);
+  const int nx = sys.nx, nu = sys.nu;
+  const int j = tid - 128;
+  double* sRed = reinterpret_cast<double*>(smem_raw + lds_bytes_forward(nx, nu, sizeof(T)) - 32 * sizeof(double));
 
-  T* sUc = reinterpret_cast<T*>(smem_raw + kRedDoubles * sizeof(double)) +
-           (size_t)kChunk * (D + 2 * nu + nx + 4);
-  T* sXc = sUc + nu;
-  for (int i = tid; i < nx; i += kBlock) sXc[i] = x.affine ? td.p[i] : T(0);
-  for (int j = tid; j < nu; j += kBlock) sUc[j] = T(0);
-  __syncthreads();
-
-  double st0 = 0.0, st1 = 0.0, st2 = 0.0;  // residual / |Hz| / |t| maxima, or power sums
-  // the root path: ancestors of this leaf chain, root first
-  const int p0 = td.path_off[wi.chain], p1 = td.path_off[wi.chain + 1];
-  for (int q = p0; q < p1; ++q) {
-    const int code = td.path[q];
-    const bool own = code < 0;
-    const ChainDesc ac = td.chains[own ? -1 - code : code];
-    fwd_segment<T, NXL>(sys, td, x, mode, ac.first, ac.len, own, smem_raw, brow, st0, st1, st2);
+  // per-thread system rows, bounds and carries of the thread's role
+  RowCache<T, kNnzB> brow[NXL];
+  T bnd[NXL][2];
+  T xc[NXL];
+#pragma unroll
+  for (int r = 0; r < NXL; ++r) {
+    const int i = lane + 64 * r;
+    const bool vi = wave < 2 && i < nx;
+    load_row(brow[r], sys.b_rp, sys.b_ci, sys.b_v, i, vi);
+    bnd[r][0] = vi ? (wave == 0 ? sys.xs[i] : sys.xmin[i]) : T(0);
+    bnd[r][1] = vi ? sys.xmax[i] : T(0);
+    xc[r] = (vi && x.affine) ? td.p[i] : T(0);
   }
+  T ubnd[2];
+  ubnd[0] = (wave >= 2 && j < nu) ? sys.umin[j] : T(0);
+  ubnd[1] = (wave >= 2 && j < nu) ? sys.umax[j] : T(0);
+  T utc = T(0);
+  int par = 0;
+  Partials pt{0.0, 0.0, 0.0};
+
+  // the root path (ancestor nodes of this leaf chain, root first), then the
+  // chain itself, as one sequence
+  const int p0 = td.path_off[wi.chain], p1 = td.path_off[wi.chain + 1];
   const ChainDesc ch = td.chains[wi.chain];
-  fwd_segment<T, NXL>(sys, td, x, mode, ch.first, ch.len, true, smem_raw, brow, st0, st1, st2);
+  fwd_nodes<T, NXL, UP>(sys, td, x, mode, td.path + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw, brow, xc,
+                        utc, bnd, ubnd, par, pt);
 
   // partials of this leaf chain
+  double s0 = pt.s0, s1 = pt.s1, s2 = pt.s2;
   if (mode == kModeAPG) {
-    st0 = wave_nanmax(st0);
-    st1 = wave_nanmax(st1);
-    st2 = wave_nanmax(st2);
+    s0 = wave_nanmax(s0);
+    s1 = wave_nanmax(s1);
+    s2 = wave_nanmax(s2);
   } else if (mode == kModePower) {
-    st0 = wave_sum(st0);
-    st1 = wave_sum(st1);
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
   }
   if (lane == 0) {
-    sRed[wave * 3 + 0] = st0;
-    sRed[wave * 3 + 1] = st1;
-    sRed[wave * 3 + 2] = st2;
+    sRed[wave * 3 + 0] = s0;
+    sRed[wave * 3 + 1] = s1;
+    sRed[wave * 3 + 2] = s2;
   }
   __syncthreads();
   if (tid == 0) {
@@ -797,22 +1006,63 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Workgroups of `kernel` that fit on the device at once (cached per kernel
+// and LDS size).
+template <typename K>
+int resident_blocks(K kernel, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, size_t, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_tuple(reinterpret_cast<const void*>(kernel), lds, dev);
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), kBlock, lds) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const int n = std::max(1, per_cu) * std::max(1, cus);
+  cache[key] = n;
+  return n;
+}
+
+template <typename T, int KP, int NXL>
+hipError_t launch_backward_kp(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+                              const double* ctab, int mode, hipStream_t s) {
+  const size_t lds = lds_bytes_backward(sys.nx, sys.nu, sizeof(T));
+  hipError_t e = allow_lds(k_backward<T, KP, NXL>, lds);
+  if (e != hipSuccess) return e;
+  const int res = resident_blocks(k_backward<T, KP, NXL>, lds);
+  if (res <= 0) return hipErrorInvalidValue;
+  const int grid = std::min(n_items, res);
+  hipLaunchKernelGGL((k_backward<T, KP, NXL>), dim3(grid), dim3(kBlock), lds, s, sys, trees, items, n_items, ctab,
+                     mode);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
                            const double* ctab, int mode, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  const size_t lds = lds_bytes_backward(sys.nx, sys.nu, sizeof(T));
-  if (sys.nu <= 64) {
-    hipError_t e = allow_lds(k_backward<T, 4, 16>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_backward<T, 4, 16>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode);
-  } else if (sys.nu <= 128) {
-    hipError_t e = allow_lds(k_backward<T, 2, 64>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_backward<T, 2, 64>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode);
-  } else {
-    return hipErrorInvalidValue;
-  }
+  if (sys.nx > 128 || sys.nu > 128) return hipErrorInvalidValue;
+  const bool x1 = sys.nx <= 64;
+  if (sys.nu <= 64)
+    return x1 ? launch_backward_kp<T, 64, 1>(sys, trees, items, n_items, ctab, mode, s)
+              : launch_backward_kp<T, 64, 2>(sys, trees, items, n_items, ctab, mode, s);
+  return x1 ? launch_backward_kp<T, 128, 1>(sys, trees, items, n_items, ctab, mode, s)
+            : launch_backward_kp<T, 128, 2>(sys, trees, items, n_items, ctab, mode, s);
+}
+
+template <typename T, int NXL, int UP>
+hipError_t launch_forward_t(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+                            const double* ctab, int mode, int32_t* done_out, hipStream_t s) {
+  const size_t lds = lds_bytes_forward(sys.nx, sys.nu, sizeof(T));
+  hipError_t e = allow_lds(k_forward<T, NXL, UP>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_forward<T, NXL, UP>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode,
+                     done_out);
   return hipGetLastError();
 }
 
@@ -820,20 +1070,12 @@ template <typename T>
 hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
                           const double* ctab, int mode, int32_t* done_out, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  const size_t lds = lds_bytes_forward(sys.nx, sys.nu, sizeof(T));
   if (sys.nu > 128 || sys.nx > 128) return hipErrorInvalidValue;
-  if (sys.nx <= 64) {
-    hipError_t e = allow_lds(k_forward<T, 1>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_forward<T, 1>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode,
-                       done_out);
-  } else {
-    hipError_t e = allow_lds(k_forward<T, 2>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_forward<T, 2>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode,
-                       done_out);
-  }
-  return hipGetLastError();
+  const bool x1 = sys.nx <= 64, u1 = sys.nu <= 64;
+  if (x1) return u1 ? launch_forward_t<T, 1, 64>(sys, trees, items, n_items, ctab, mode, done_out, s)
+                    : launch_forward_t<T, 1, 128>(sys, trees, items, n_items, ctab, mode, done_out, s);
+  return u1 ? launch_forward_t<T, 2, 64>(sys, trees, items, n_items, ctab, mode, done_out, s)
+            : launch_forward_t<T, 2, 128>(sys, trees, items, n_items, ctab, mode, done_out, s);
 }
 
 template <typename T>
