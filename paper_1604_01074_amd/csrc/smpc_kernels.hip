@@ -39,6 +39,26 @@ namespace smpc {
 
 namespace {
 
+// Pointers read from the tree and system tables are generic; accesses through
+// them compile to FLAT instructions, whose completion the hardware counts
+// with the LDS counter as well (a wait for LDS data would also wait for
+// outstanding HBM loads).  Every device array lives in global memory, so the
+// kernels access it through address-space-1 pointers.
+// (The host compilation pass never runs these functions; there the alias is
+// the plain type.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using G = __attribute__((address_space(1))) T;
+#else
+template <typename T>
+using G = T;
+#endif
+
+template <typename T>
+__device__ __forceinline__ G<T>* gp(T* p) {
+  return (G<T>*)p;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -69,12 +89,12 @@ __device__ __forceinline__ T clampv(T a, T lo, T hi) {
 // invalidating a whole L2 (what a device-scope fence does).
 template <typename T>
 __device__ __forceinline__ void st_agent(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(gp(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T>
 __device__ __forceinline__ T ld_agent(const T* p) {
-  return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(const_cast<T*>(p)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Wait until this wave's memory operations have completed (stores
@@ -106,13 +126,13 @@ __device__ __forceinline__ void wait_mem() {
 // MFMA tiles.
 template <typename T>
 struct ChunkLen {
-  static constexpr int value = sizeof(T) == 4 ? 32 : 16;
+  static constexpr int value = 16;
 };
 
 // Nodes per forward chunk (register arrays of this length per thread).
 template <typename T>
 struct FwdChunk {
-  static constexpr int value = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int value = 8;
 };
 
 // 16x16x4 matrix-core products.  Operand layouts (both precisions): lane l
@@ -161,14 +181,14 @@ __device__ __forceinline__ void load_row(RowCache<T, K>& r, const int32_t* rp, c
                                          int row, bool valid) {
   r.n = r.q0 = r.q1 = 0;
   if (valid) {
-    r.q0 = rp[row];
-    r.q1 = rp[row + 1];
+    r.q0 = gp(rp)[row];
+    r.q1 = gp(rp)[row + 1];
     r.n = r.q1 - r.q0;
   }
 #pragma unroll
   for (int q = 0; q < K; ++q) {
-    r.c[q] = q < r.n ? ci[r.q0 + q] : 0;
-    r.w[q] = q < r.n ? v[r.q0 + q] : T(0);
+    r.c[q] = q < r.n ? gp(ci)[r.q0 + q] : 0;
+    r.w[q] = q < r.n ? gp(v)[r.q0 + q] : T(0);
   }
 }
 
@@ -220,13 +240,13 @@ struct Iter {
   int it;
   T c, in_scale, lam, ilam;
   bool affine, scaled, write_z;
-  const T* ycur;
-  const T* yprv;
-  T* ynew;
+  const G<T>* ycur;
+  const G<T>* yprv;
+  G<T>* ynew;
 };
 
 template <typename T>
-__device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const TreeState* st, const double* ctab,
+__device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const G<TreeState>* st, const double* ctab,
                                              int mode) {
   Iter<T> x;
   x.it = st->iter;
@@ -235,7 +255,7 @@ __device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const TreeSta
   x.lam = T(1);
   x.ilam = T(1);
   if (mode == kModeAPG) {
-    x.c = (T)ctab[x.it];
+    x.c = (T)gp(ctab)[x.it];
     x.lam = (T)st->lambda;
     x.ilam = T(1) / x.lam;
   }
@@ -244,16 +264,16 @@ __device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const TreeSta
   x.scaled = (td.scale != nullptr) && (mode != kModeSolve);
   const bool check = (mode != kModeAPG) || ((x.it + 1) % st->check_every == 0) || (x.it + 1 >= st->max_iter);
   x.write_z = (mode == kModeSolve) || (mode == kModeAPG && check);
-  x.ycur = td.y[x.it % 3];
-  x.yprv = td.y[(x.it + 2) % 3];
-  x.ynew = td.y[(x.it + 1) % 3];
+  x.ycur = gp(td.y[x.it % 3]);
+  x.yprv = gp(td.y[(x.it + 2) % 3]);
+  x.ynew = gp(td.y[(x.it + 1) % 3]);
   return x;
 }
 
 // The dual point the solve step is evaluated at: the extrapolated
 // w = y + c (y - y_prev) (APG), the normalised power-iteration vector, or y.
 template <typename T>
-__device__ __forceinline__ T wpoint(const Iter<T>& x, int mode, size_t k) {
+__device__ __forceinline__ T wpoint(const Iter<T>& x, int mode, uint32_t k) {
   const T y = x.ycur[k];
   if (mode == kModeAPG) return y + x.c * (y - x.yprv[k]);
   if (mode == kModePower) return x.in_scale * y;
@@ -309,7 +329,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
   const int nx = sys.nx, nu = sys.nu, D = sys.D;
   const int j = tid - 128;
   const bool ju = wave >= 2 && j < nu;
-  const ChainDesc ch = td.chains[chain];
+  const ChainDesc ch = gp(td.chains)[chain];
 
   T* sQ = reinterpret_cast<T*>(smem_raw);  // 2 x CH x XS: Q parts of waves 0, 1
   T* sRt = sQ + 2 * CH * XS;               // KP x RS: sRt[j * RS + cc]; rows nu..KP-1 zero
@@ -358,7 +378,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
     const int C = top - k0;
     const int nb = ch.first + k0;  // internal index of the chunk's first node
     T* sIp = sI + par * CH;
-    if (tid < C) sIp[tid] = T(-0.5) / td.pi[nb + tid];
+    if (tid < C) sIp[tid] = T(-0.5) / gp(td.pi)[nb + tid];
     if (wave < 2) {
       // this wave's part of xi_n (block b = wave); with A = I the Q recursion
       // runs along, bottom node first
@@ -370,8 +390,8 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
 #pragma unroll
         for (int cc = CH - 1; cc >= 0; --cc) {
           if (cc < C && i < nx) {
-            const size_t n = (size_t)(nb + cc);
-            const T sb = x.scaled ? td.scale[n * 3 + b] : T(1);
+            const uint32_t n = (uint32_t)(nb + cc);
+            const T sb = x.scaled ? gp(td.scale)[n * 3 + b] : T(1);
             const T xi = sb * wpoint(x, mode, n * D + b * nx + i);
             if (sys.a_identity) {
               qc[r] += xi;
@@ -399,7 +419,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
             q[r] = T(0);
             if (i < nx) {
               q[r] = sQw[cc * XS + i];
-              for (int k = sys.at_rp[i]; k < sys.at_rp[i + 1]; ++k) q[r] += sys.at_v[k] * cq[sys.at_ci[k]];
+              for (int k = gp(sys.at_rp)[i]; k < gp(sys.at_rp)[i + 1]; ++k) q[r] += gp(sys.at_v)[k] * cq[gp(sys.at_ci)[k]];
             }
           }
           __builtin_amdgcn_wave_barrier();
@@ -420,9 +440,9 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
 #pragma unroll
       for (int cc = 0; cc < CH; ++cc)
         if (cc < C) {
-          const size_t n = (size_t)(nb + cc);
-          const T s2 = x.scaled ? td.scale[n * 3 + 2] : T(1);
-          sRt[j * RS + cc] = (x.affine ? td.beta[n * nu + j] : T(0)) + s2 * wpoint(x, mode, n * D + 2 * nx + j);
+          const uint32_t n = (uint32_t)(nb + cc);
+          const T s2 = x.scaled ? gp(td.scale)[n * 3 + 2] : T(1);
+          sRt[j * RS + cc] = (x.affine ? gp(td.beta)[n * nu + j] : T(0)) + s2 * wpoint(x, mode, n * D + 2 * nx + j);
         }
     }
     __syncthreads();  // Q parts complete
@@ -438,7 +458,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
             for (int q = 0; q < kNnzBt; ++q) g += bt.w[q] * (sQ[cc * XS + bt.c[q]] + sQz[cc * XS + bt.c[q]]);
           } else {
             for (int q = bt.q0; q < bt.q1; ++q)
-              g += sys.bt_v[q] * (sQ[cc * XS + sys.bt_ci[q]] + sQz[cc * XS + sys.bt_ci[q]]);
+              g += gp(sys.bt_v)[q] * (sQ[cc * XS + gp(sys.bt_ci)[q]] + sQz[cc * XS + gp(sys.bt_ci)[q]]);
           }
           rc += g;
           sRt[j * RS + cc] = rc;
@@ -472,7 +492,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int cc = 16 * m + Mfma<T>::row(lane, r);
-          if (cc < C && jj < nu) td.du[(size_t)(nb + cc) * nu + jj] = acc[m][t][r] * sIp[cc];
+          if (cc < C && jj < nu) gp(td.du)[(uint32_t)(nb + cc) * (uint32_t)nu + jj] = acc[m][t][r] * sIp[cc];
         }
       }
     par ^= 1;
@@ -515,7 +535,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
   for (int st = 0; st < KS; ++st)
 #pragma unroll
     for (int t = 0; t < NT; ++t)
-      preg[st * NT + t] = sys.P[(size_t)(4 * st + (lane >> 4)) * KP + 16 * (wave * NT + t) + (lane & 15)];
+      preg[st * NT + t] = gp(sys.P)[(size_t)(4 * st + (lane >> 4)) * KP + 16 * (wave * NT + t) + (lane & 15)];
   RowCache<T, kNnzBt> bt;
   load_row(bt, sys.bt_rp, sys.bt_ci, sys.bt_v, tid - 128, wave >= 2 && tid - 128 < nu);
   {
@@ -529,22 +549,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const WorkItem wi = items[item];
     const TreeDev<T>& td = trees[wi.tree];
-    const TreeState* st = td.st;
+    const G<TreeState>* st = gp(td.st);
     if (st->done) continue;
     const Iter<T> x = make_iter(td, st, ctab, mode);
     int chain = wi.chain;
     while (true) {
       bwd_chain<T, KP, NXL>(sys, td, x, mode, chain, smem_raw, preg, bt, par);
-      const int parent = td.chains[chain].parent;
+      const int parent = gp(td.chains)[chain].parent;
       if (parent < 0) break;  // the root chain is done: the sweep is complete
       // this chain's top terms are stored: count this child done at the parent
       wait_mem();
       __syncthreads();
       if (tid == 0) {
-        const int pc = td.chains[parent].child_count;
-        const int prev = __hip_atomic_fetch_add(&td.cnt[parent], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int pc = gp(td.chains)[parent].child_count;
+        const int prev = __hip_atomic_fetch_add(gp(td.cnt) + parent, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_last = (prev == pc - 1);
-        if (s_last) st_agent(&td.cnt[parent], 0);  // ready for the next iteration
+        if (s_last) __hip_atomic_store(gp(td.cnt) + parent, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next iteration
       }
       __syncthreads();
       if (!s_last) break;  // a sibling is still running; it will sweep the parent
@@ -569,18 +589,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
 // ---------------------------------------------------------------------------
 struct Partials {
   double s0, s1, s2;  // residual / |Hz| / |t| maxima, or power-iteration sums
+  bool nan;           // a NaN met on the way (fmax would drop it)
 };
 
 __device__ __forceinline__ void fold_max(Partials& p, double hz, double t) {
-  p.s0 = nanmax(p.s0, fabs(hz - t));
-  p.s1 = nanmax(p.s1, fabs(hz));
-  p.s2 = nanmax(p.s2, fabs(t));
+  const double r = hz - t;
+  p.nan |= (r != r);
+  p.s0 = fmax(p.s0, fabs(r));
+  p.s1 = fmax(p.s1, fabs(hz));
+  p.s2 = fmax(p.s2, fabs(t));
 }
 
 // The extrapolated dual point from explicit arrays (see wpoint).
 template <typename T>
-__device__ __forceinline__ T wpoint2(int mode, T c, T in_scale, const T* __restrict__ yc, const T* __restrict__ yp,
-                                     size_t k) {
+__device__ __forceinline__ T wpoint2(int mode, T c, T in_scale, const G<T>* __restrict__ yc,
+                                     const G<T>* __restrict__ yp, uint32_t k) {
   const T y = yc[k];
   if (mode == kModeAPG) return y + c * (y - yp[k]);
   if (mode == kModePower) return in_scale * y;
@@ -589,7 +612,7 @@ __device__ __forceinline__ T wpoint2(int mode, T c, T in_scale, const T* __restr
 
 // Entry k of a leaf chain's forward sequence: the plen root-path codes, then
 // the chain's own nodes from `first` (owned: -1 - node).
-__device__ __forceinline__ int32_t node_code(const int32_t* __restrict__ codes, int plen, int first, int k) {
+__device__ __forceinline__ int32_t node_code(const G<int32_t>* __restrict__ codes, int plen, int first, int k) {
   return k < plen ? codes[k] : -1 - (first + k - plen);
 }
 
@@ -598,12 +621,12 @@ __device__ __forceinline__ int32_t node_code(const int32_t* __restrict__ codes, 
 // allocations (the three dual slots rotate), so the loads of later nodes may
 // be issued before the stores of earlier ones.
 template <typename T, int UP>
-__device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const int32_t* __restrict__ codes,
+__device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const G<int32_t>* __restrict__ codes,
                                               int plen, int first, int k0, int C, int j, int nx, int nu, int D,
-                                              const T* __restrict__ du, const T* __restrict__ uhat,
-                                              const T* __restrict__ yc, const T* __restrict__ yp,
-                                              const T* __restrict__ scale, T* __restrict__ ynew,
-                                              T* __restrict__ z, T* sUp, T& utc, T ulo, T uhi, Partials& pt) {
+                                              const G<T>* __restrict__ du, const G<T>* __restrict__ uhat,
+                                              const G<T>* __restrict__ yc, const G<T>* __restrict__ yp,
+                                              const G<T>* __restrict__ scale, G<T>* __restrict__ ynew,
+                                              G<T>* __restrict__ z, T* sUp, T& utc, T ulo, T uhi, Partials& pt) {
   constexpr int CH = FwdChunk<T>::value;
   constexpr int US = UP;
   const int W = nx + nu;
@@ -616,7 +639,7 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const 
     sv[cc] = T(1);
     if (cc < C) {
       const int32_t code = node_code(codes, plen, first, k0 + cc);
-      const size_t n = (size_t)(code < 0 ? -1 - code : code);
+      const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
       duv[cc] = du[n * nu + j];
       if (x.affine) uhv[cc] = uhat[n * nu + j];
       if (mode != kModeSolve) {
@@ -630,7 +653,7 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const 
     if (cc < C) {
       const int32_t code = node_code(codes, plen, first, k0 + cc);
       const bool own = code < 0;
-      const size_t n = (size_t)(own ? -1 - code : code);
+      const uint32_t n = (uint32_t)(own ? -1 - code : code);
       utc += duv[cc];
       sUp[cc * US + j] = utc;
       if (own) {
@@ -661,12 +684,12 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const 
 // the dual update.
 template <typename T, int NXL, int UP>
 __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T>& x, int b,
-                                                const int32_t* __restrict__ codes, int plen, int first, int k0,
+                                                const G<int32_t>* __restrict__ codes, int plen, int first, int k0,
                                                 int C,
                                                 const T (&ev)[NXL][FwdChunk<T>::value],
                                                 const T (&wv)[NXL][FwdChunk<T>::value],
                                                 const RowCache<T, kNnzB> (&brow)[NXL], const T (&bnd)[NXL][2],
-                                                const T* sSP, T* __restrict__ ynew, T* __restrict__ z,
+                                                const T* sSP, G<T>* __restrict__ ynew, G<T>* __restrict__ z,
                                                 const T* sUp, T* cx, T (&xc)[NXL], Partials& pt) {
   constexpr int CH = FwdChunk<T>::value;
   constexpr int US = UP;
@@ -693,7 +716,7 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
 #pragma unroll
             for (int q = 0; q < kNnzB; ++q) g += brow[r].w[q] * sUp[cc * US + brow[r].c[q]];
           } else {
-            for (int q = brow[r].q0; q < brow[r].q1; ++q) g += sys.b_v[q] * sUp[cc * US + sys.b_ci[q]];
+            for (int q = brow[r].q0; q < brow[r].q1; ++q) g += gp(sys.b_v)[q] * sUp[cc * US + gp(sys.b_ci)[q]];
           }
           xc[r] += g;
           xn[r] = xc[r];
@@ -709,8 +732,8 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
         xn[r] = T(0);
         if (i < nx) {
           T g = ev[r][cc];
-          for (int q = sys.a_rp[i]; q < sys.a_rp[i + 1]; ++q) g += sys.a_v[q] * cx[sys.a_ci[q]];
-          for (int q = sys.b_rp[i]; q < sys.b_rp[i + 1]; ++q) g += sys.b_v[q] * sUp[cc * US + sys.b_ci[q]];
+          for (int q = gp(sys.a_rp)[i]; q < gp(sys.a_rp)[i + 1]; ++q) g += gp(sys.a_v)[q] * cx[gp(sys.a_ci)[q]];
+          for (int q = gp(sys.b_rp)[i]; q < gp(sys.b_rp)[i + 1]; ++q) g += gp(sys.b_v)[q] * sUp[cc * US + gp(sys.b_ci)[q]];
           xn[r] = g;
         }
       }
@@ -726,7 +749,7 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
     }
     const int32_t code = node_code(codes, plen, first, k0 + cc);
     if (code >= 0) continue;  // wave-uniform: the node is owned elsewhere
-    const size_t n = (size_t)(-1 - code);
+    const uint32_t n = (uint32_t)(-1 - code);
     if (x.write_z && b == 0) {
 #pragma unroll
       for (int r = 0; r < NXL; ++r)
@@ -776,7 +799,7 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
 
 template <typename T, int NXL, int UP>
 __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode,
-                          const int32_t* codes, int plen, int first, int len, unsigned char* smem_raw,
+                          const G<int32_t>* codes, int plen, int first, int len, unsigned char* smem_raw,
                           const RowCache<T, kNnzB> (&brow)[NXL], T (&xc)[NXL], T& utc, const T (&bnd)[NXL][2],
                           const T (&ubnd)[2], int& par, Partials& pt) {
   constexpr int CH = FwdChunk<T>::value;
@@ -796,14 +819,14 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
     T* sSPp = sSP + par * 4 * CH;
     if (tid < C) {
       const int32_t code = node_code(codes, plen, first, k0 + tid);
-      const size_t n = (size_t)(code < 0 ? -1 - code : code);
-      sSPp[4 * tid] = x.scaled ? td.scale[n * 3] : T(1);
-      sSPp[4 * tid + 1] = x.scaled ? td.scale[n * 3 + 1] : T(1);
-      sSPp[4 * tid + 3] = td.pi[n];
+      const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
+      sSPp[4 * tid] = x.scaled ? gp(td.scale)[n * 3] : T(1);
+      sSPp[4 * tid + 1] = x.scaled ? gp(td.scale)[n * 3 + 1] : T(1);
+      sSPp[4 * tid + 3] = gp(td.pi)[n];
     }
     if (ju)
-      fwd_psi_chunk<T, UP>(mode, x, codes, plen, first, k0, C, j, nx, nu, D, td.du, td.uhat, x.ycur, x.yprv, td.scale,
-                       x.ynew, td.z, sUp, utc, ubnd[0], ubnd[1], pt);
+      fwd_psi_chunk<T, UP>(mode, x, codes, plen, first, k0, C, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur,
+                           x.yprv, gp(td.scale), x.ynew, gp(td.z), sUp, utc, ubnd[0], ubnd[1], pt);
     // waves 0, 1: e and the dual point of the wave's block, loaded before the
     // barrier
     const int b = wave;  // 0: sigma~, 1: zeta~
@@ -819,8 +842,8 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
           if (cc < C && i < nx) {
             const int32_t code = node_code(codes, plen, first, k0 + cc);
             const bool own = code < 0;
-            const size_t n = (size_t)(own ? -1 - code : code);
-            if (x.affine) ev[r][cc] = td.e[n * nx + i];
+            const uint32_t n = (uint32_t)(own ? -1 - code : code);
+            if (x.affine) ev[r][cc] = gp(td.e)[n * nx + i];
             if (own && mode != kModeSolve) wv[r][cc] = wpoint(x, mode, n * D + b * nx + i);
           }
         }
@@ -828,7 +851,7 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
     }
     __syncthreads();  // ut of the chunk published
     if (wave < 2)
-      fwd_state_chunk<T, NXL, UP>(sys, mode, x, b, codes, plen, first, k0, C, ev, wv, brow, bnd, sSPp, x.ynew, td.z, sUp,
+      fwd_state_chunk<T, NXL, UP>(sys, mode, x, b, codes, plen, first, k0, C, ev, wv, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
                                   sXc + (size_t)wave * nx, xc, pt);
     par ^= 1;
   }
@@ -846,7 +869,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
   const int wave = tid >> 6;
   const WorkItem wi = items[blockIdx.x];
   const TreeDev<T>& td = trees[wi.tree];
-  TreeState* st = td.st;
+  G<TreeState>* st = gp(td.st);
   if (st->done) {
     if (tid == 0) done_out[wi.tree] = 1;
     return;
@@ -865,26 +888,27 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
     const int i = lane + 64 * r;
     const bool vi = wave < 2 && i < nx;
     load_row(brow[r], sys.b_rp, sys.b_ci, sys.b_v, i, vi);
-    bnd[r][0] = vi ? (wave == 0 ? sys.xs[i] : sys.xmin[i]) : T(0);
-    bnd[r][1] = vi ? sys.xmax[i] : T(0);
-    xc[r] = (vi && x.affine) ? td.p[i] : T(0);
+    bnd[r][0] = vi ? (wave == 0 ? gp(sys.xs)[i] : gp(sys.xmin)[i]) : T(0);
+    bnd[r][1] = vi ? gp(sys.xmax)[i] : T(0);
+    xc[r] = (vi && x.affine) ? gp(td.p)[i] : T(0);
   }
   T ubnd[2];
-  ubnd[0] = (wave >= 2 && j < nu) ? sys.umin[j] : T(0);
-  ubnd[1] = (wave >= 2 && j < nu) ? sys.umax[j] : T(0);
+  ubnd[0] = (wave >= 2 && j < nu) ? gp(sys.umin)[j] : T(0);
+  ubnd[1] = (wave >= 2 && j < nu) ? gp(sys.umax)[j] : T(0);
   T utc = T(0);
   int par = 0;
-  Partials pt{0.0, 0.0, 0.0};
+  Partials pt{0.0, 0.0, 0.0, false};
 
   // the root path (ancestor nodes of this leaf chain, root first), then the
   // chain itself, as one sequence
-  const int p0 = td.path_off[wi.chain], p1 = td.path_off[wi.chain + 1];
-  const ChainDesc ch = td.chains[wi.chain];
-  fwd_nodes<T, NXL, UP>(sys, td, x, mode, td.path + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw, brow, xc,
+  const int p0 = gp(td.path_off)[wi.chain], p1 = gp(td.path_off)[wi.chain + 1];
+  const ChainDesc ch = gp(td.chains)[wi.chain];
+  fwd_nodes<T, NXL, UP>(sys, td, x, mode, gp(td.path) + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw, brow, xc,
                         utc, bnd, ubnd, par, pt);
 
   // partials of this leaf chain
-  double s0 = pt.s0, s1 = pt.s1, s2 = pt.s2;
+  const double qnan = __longlong_as_double(0x7ff8000000000000LL);
+  double s0 = pt.nan ? qnan : pt.s0, s1 = pt.s1, s2 = pt.s2;
   if (mode == kModeAPG) {
     s0 = wave_nanmax(s0);
     s1 = wave_nanmax(s1);
@@ -900,7 +924,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
   }
   __syncthreads();
   if (tid == 0) {
-    double* out = td.cstat + (size_t)wi.chain * kStat;
+    double* out = gp(td.cstat) + (size_t)wi.chain * kStat;
     double a0 = sRed[0], a1 = sRed[1], a2 = sRed[2];
     for (int w = 1; w < kBlock / 64; ++w) {
       if (mode == kModeAPG) {
@@ -935,7 +959,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
     if (check) {
       double rm = 0.0, hm = 0.0;
       for (int k = lane; k < td.n_leaves; k += 64) {
-        const double* cs = td.cstat + (size_t)td.leaves[k] * kStat;
+        const double* cs = td.cstat + (size_t)gp(td.leaves)[k] * kStat;
         rm = nanmax(rm, ld_agent(&cs[0]));
         hm = nanmax(hm, ld_agent(&cs[1]));
         hm = nanmax(hm, ld_agent(&cs[2]));
@@ -963,14 +987,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
       }
     }
     if (lane == 0) {
-      st_agent(&st->fwd_count, 0);
+      __hip_atomic_store(&st->fwd_count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       st->iter = it + 1;
       done_out[wi.tree] = done;
     }
   } else {  // power iteration: Rayleigh quotient and normalisation
     double gg = 0.0, wg = 0.0;
     for (int k = lane; k < td.n_leaves; k += 64) {
-      const double* cs = td.cstat + (size_t)td.leaves[k] * kStat;
+      const double* cs = td.cstat + (size_t)gp(td.leaves)[k] * kStat;
       gg += ld_agent(&cs[0]);
       wg += ld_agent(&cs[1]);
     }
@@ -979,7 +1003,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
     if (lane == 0) {
       st->lmax_est = wg;
       st->in_scale = gg > 0.0 ? 1.0 / sqrt(gg) : 0.0;
-      st_agent(&st->fwd_count, 0);
+      __hip_atomic_store(&st->fwd_count, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       st->iter = it + 1;
       done_out[wi.tree] = 0;
     }
