@@ -147,7 +147,11 @@ int smpc_tree_info(smpc_tree* tree, int* M, int* N, int* n_chains, int* n_levels
  * precision 64: every step in float64.  precision 32: the solve step, prox and
  * extrapolation run in float32 until the stop test passes (or max_iter -
  * polish_iters is reached), then polish_iters more iterations run in float64
- * from the float32 dual iterates.  Reductions are float64 in both modes.
+ * from the float32 dual iterates.  A float32 phase whose r_p has not fallen
+ * below 0.99 of its best value for stall_checks consecutive checks has met
+ * the accuracy floor of float32: that tree continues in float64 until the
+ * stop test passes or max_iter is reached (stall_checks 0 -> 100, < 0 ->
+ * never; not applied when tol = 0).  Reductions are float64 in both modes.
  * warm_start: 0 -> y0 = 0; 2 -> y^0 = y0 and y^{-1} = y_prev0 (or y0 when
  * y_prev0 is NULL), both M*(2nx+nu) in the caller's node order.            */
 typedef struct {
@@ -159,6 +163,7 @@ typedef struct {
   int warm_start;
   const double* y0;
   const double* y_prev0;
+  int stall_checks;
 } smpc_solve_opts;
 
 /* Caller-allocated outputs; any pointer may be NULL.  u0: nu, x: M*nx,

@@ -630,7 +630,7 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
       off += (size_t)t->M * D;
     }
   }
-  auto init_state = [&](smpc_tree* t, int iter, int max_iter, double tol) {
+  auto init_state = [&](smpc_tree* t, int iter, int max_iter, double tol, int stall_limit) {
     TreeState h{};
     h.iter = iter;
     h.done = 0;
@@ -641,10 +641,17 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
     h.tol = tol;
     h.lambda = t->lambda;
     h.in_scale = 1.0;
+    h.best_rp = HUGE_VAL;
+    h.stall = 0;
+    h.stall_limit = stall_limit;
     return write_state(t, h);
   };
+  // float32 phase: stop at the stop test, at max_iter - polish, or when r_p
+  // has stalled at float32's accuracy floor (status 2)
+  // (a fixed iteration count, tol = 0, is never cut short)
+  const int stall32 = o->tol <= 0.0 || o->stall_checks < 0 ? 0 : (o->stall_checks == 0 ? 100 : o->stall_checks);
   if (run32) {
-    for (int k = 0; k < n; ++k) SMPC_TRY(init_state(plan->trees[k], 0, max32, o->tol));
+    for (int k = 0; k < n; ++k) SMPC_TRY(init_state(plan->trees[k], 0, max32, o->tol, stall32));
     SMPC_TRY(run_until_done<float>(ctx, sys, plan, o->check_every, max_rounds));
     for (int k = 0; k < n; ++k) {
       TreeState h;
@@ -664,22 +671,25 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
         for (int s = 0; s < 3; ++s)
           HIP_TRY(launch_widen<float>((const float*)b32.y[s].ptr, (double*)b64.y[s].ptr, (size_t)t->M * D, ctx->stream));
         if (status32[k] == -9) {
-          SMPC_TRY(init_state(t, fp32_iters[k], fp32_iters[k], 0.0));
+          SMPC_TRY(init_state(t, fp32_iters[k], fp32_iters[k], 0.0, 0));
           TreeState h;
           SMPC_TRY(read_state(t, &h));
           h.done = 1;
           h.status = -9;
           h.iters_done = fp32_iters[k];
           SMPC_TRY(write_state(t, h));
+        } else if (status32[k] == 2) {
+          // stalled in float32: continue in float64 to the stop test
+          SMPC_TRY(init_state(t, fp32_iters[k], o->max_iter, o->tol, 0));
         } else {
-          SMPC_TRY(init_state(t, fp32_iters[k], fp32_iters[k] + polish, 0.0));
+          // float32 met the stop test or the float32 budget: polish
+          SMPC_TRY(init_state(t, fp32_iters[k], fp32_iters[k] + polish, 0.0, 0));
         }
       } else {
-        SMPC_TRY(init_state(t, 0, o->max_iter, o->tol));
+        SMPC_TRY(init_state(t, 0, o->max_iter, o->tol, 0));
       }
     }
-    SMPC_TRY(run_until_done<double>(ctx, sys, plan, use32 ? std::max(1, std::min(o->check_every, polish)) : o->check_every,
-                                    max_rounds + polish + 2));
+    SMPC_TRY(run_until_done<double>(ctx, sys, plan, o->check_every, max_rounds + polish + 2));
   }
   for (int k = 0; k < n; ++k) {
     smpc_tree* t = plan->trees[k];
@@ -693,7 +703,7 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
     r->hz_t_max = h.hzt;
     int status;
     if (h.status == -9 || (run32 && status32[k] == -9)) status = SMPC_EDIVERGED;
-    else if (run32) status = status32[k] == 0 ? SMPC_OK : SMPC_MAX_ITER;
+    else if (run32 && status32[k] != 2) status = status32[k] == 0 ? SMPC_OK : SMPC_MAX_ITER;
     else status = h.status == 0 ? SMPC_OK : SMPC_MAX_ITER;
     r->status = status;
     if (run64) {

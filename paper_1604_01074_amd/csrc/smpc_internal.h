@@ -54,7 +54,7 @@ struct TreeState {
   int32_t done;         // 1 -> kernels skip this tree
   int32_t max_iter;     // stop after this many iterations
   int32_t check_every;  // residual test period
-  int32_t status;       // 0 converged, 1 max_iter, -9 diverged
+  int32_t status;       // 0 converged, 1 max_iter, 2 stalled, -9 diverged
   int32_t iters_done;   // iterations when the tree stopped
   int32_t fwd_count;    // leaf chains finished in the current forward kernel
   int32_t pad1;
@@ -64,6 +64,9 @@ struct TreeState {
   double hzt;           // last max(||Hz||_inf, ||t||_inf)
   double in_scale;      // power iteration: 1 / ||g_k||
   double lmax_est;      // power iteration: Rayleigh quotient
+  double best_rp;       // smallest r_p seen at a check (stall detection)
+  int32_t stall;        // checks since r_p last fell below 0.99 best_rp
+  int32_t stall_limit;  // stop with status 2 after this many; 0 = never
 };
 
 template <typename T>

@@ -979,6 +979,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
         } else if (it + 1 >= st->max_iter) {
           done = 1;
           st->status = 1;
+        } else if (st->stall_limit > 0) {
+          // no new minimum of r_p for stall_limit checks: the iteration has
+          // reached the accuracy floor of its number format
+          if (rm < 0.99 * st->best_rp) {
+            st->best_rp = rm;
+            st->stall = 0;
+          } else if (++st->stall >= st->stall_limit) {
+            done = 1;
+            st->status = 2;
+          }
         }
         if (done) {
           st->done = 1;

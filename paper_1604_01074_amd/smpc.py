@@ -79,7 +79,7 @@ class FactorOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("precision", C.c_int), ("polish_iters", C.c_int), ("warm_start", C.c_int),
-                ("y0", _dp), ("y_prev0", _dp)]
+                ("y0", _dp), ("y_prev0", _dp), ("stall_checks", C.c_int)]
 
 
 class Result(C.Structure):
@@ -234,10 +234,10 @@ def smpc_tree_get_factor(t, with_scale: bool = False):
 
 # ---------------------------------------------------------------- solve
 
-def _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0):
+def _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks=0):
     keep = [None if y0 is None else _f64(y0), None if y_prev0 is None else _f64(y_prev0)]
     o = SolveOpts(float(tol), int(max_iter), int(check_every), int(precision), int(polish_iters),
-                  2 if y0 is not None else 0, _ptr(keep[0]), _ptr(keep[1]))
+                  2 if y0 is not None else 0, _ptr(keep[0]), _ptr(keep[1]), int(stall_checks))
     return o, keep
 
 
@@ -260,11 +260,11 @@ def _finish(r: Result, out: dict) -> dict:
 
 
 def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precision=64, polish_iters=0,
-               y0=None, y_prev0=None, want_x=True, want_y=True) -> dict:
+               y0=None, y_prev0=None, want_x=True, want_y=True, stall_checks=0) -> dict:
     """``dims = (M, nx, nu)``.  Returns a dict with u0, x, u, y, iterations,
     fp32_iterations, r_primal, hz_t_max, status."""
     M, nx, nu = dims
-    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0)
+    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks)
     r, out = _result(M, nx, nu, want_x, want_y)
     pp, qq = _f64(p), _f64(q)
     _check_solve(_lib.smpc_solve(t, _ptr(pp), _ptr(qq), C.byref(o), C.byref(r)))
@@ -272,9 +272,10 @@ def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precis
 
 
 def smpc_solve_batch(trees, ps, qs, *, dims_list, tol=1e-3, max_iter=1000, check_every=10, precision=64,
-                     polish_iters=0, y0=None, y_prev0=None, want_x=True, want_y=True) -> tuple[int, list]:
+                     polish_iters=0, y0=None, y_prev0=None, want_x=True, want_y=True,
+                     stall_checks=0) -> tuple[int, list]:
     n = len(trees)
-    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0)
+    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks)
     res = (Result * n)()
     outs = []
     for k, (M, nx, nu) in enumerate(dims_list):

@@ -173,6 +173,34 @@ def test_apg_fp32_polish_tiny(ctx):
     assert abs(c_g - c_o) <= 2e-3 * abs(c_o)
 
 
+def test_fp32_stall_continues_in_fp64(ctx):
+    """With a short stall window the float32 phase stops early (no new
+    minimum of r_p for stall_checks checks), the tree continues in float64 and
+    meets the stop test; with stall detection off the float32 phase runs its
+    whole budget instead."""
+    inst = ds.tiny_instance()
+    s = ctx.system(inst.sys)
+    try:
+        t = s.tree(inst.tree)
+        t.set_data(inst.d, inst.alpha2)
+        t.factor(precond=0, power_iters=100)
+        kw = dict(tol=2e-5, max_iter=20000, check_every=10, precision=32, polish_iters=20)
+        r = t.solve(inst.p, inst.q, stall_checks=5, **kw)
+        print(f"[stall] fp32 {r['fp32_iterations']} total {r['iterations']} r_p {r['r_primal']:.3e}", flush=True)
+        assert r["status"] == 0
+        assert 0 < r["fp32_iterations"] < r["iterations"] - 20
+        assert r["r_primal"] <= 2e-5 * (1 + r["hz_t_max"])
+        r64 = t.solve(inst.p, inst.q, tol=2e-5, max_iter=20000, check_every=10, precision=64)
+        assert r64["status"] == 0
+        # two iterates that both pass the stop test: close, not equal
+        assert np.max(np.abs(r["u0"] - r64["u0"])) <= 1e-2 * max(1.0, np.max(np.abs(r64["u0"])))
+        off = t.solve(inst.p, inst.q, stall_checks=-1, **dict(kw, tol=1e-9, max_iter=3000))
+        assert off["status"] == 1 and off["fp32_iterations"] == 2980 and off["iterations"] == 3000
+    finally:
+        s.close()
+        ctx.systems.remove(s)
+
+
 def test_apg_tolerance_stop_matches_oracle(ctx):
     inst = ds.tiny_instance()
     g, r, P = _apg_pair(ctx, inst, 5000, tol=1e-3, check_every=10)
