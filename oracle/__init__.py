@@ -21,6 +21,8 @@ from .smpc_oracle import (
     primal_cost,
     dual_hessian_dense,
     dual_lmax_power,
+    shift_map,
+    shift_dual,
 )
 
 __all__ = [
@@ -37,4 +39,6 @@ __all__ = [
     "primal_cost",
     "dual_hessian_dense",
     "dual_lmax_power",
+    "shift_map",
+    "shift_dual",
 ]

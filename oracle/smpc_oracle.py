@@ -517,3 +517,46 @@ def dual_lmax_power(P: OracleProblem, iters: int = 300, F: Factor | None = None,
             return 0.0
         w = g / nrm
     return lam
+
+
+# ---------------------------------------------------------------------------
+# Receding-horizon warm start (closed loop of Alg. 2)
+#
+# The paper starts every MPC step from y0 = 0; any dual point is a valid start
+# for the APG, so a served controller may start from the previous step's dual
+# moved one stage forward.  Reading used here (the paper does not define a
+# shift): the new root takes the place of the realised stage-1 child of the old
+# root; a new node at stage j + 1 takes the place of the child of its parent's
+# image with the same child index (the last child when there are fewer); below
+# the old last stage the image stays put (the last stage is duplicated).  Dual
+# blocks whose cost is probability weighted (the safety distance when
+# ``weight_safety_by_prob``, the input box of the probability-weighted input
+# costs) are rescaled by pi_new / pi_old; the state-box block is kept.
+# ---------------------------------------------------------------------------
+def shift_map(P: OracleProblem, realized: int) -> np.ndarray:
+    """Image ``m(n)`` in the previous tree of every node ``n`` of the next
+    tree (the same tree structure one stage later)."""
+    ch = P.children()
+    if not 0 <= realized < len(ch[0]):
+        raise ValueError("realized must index a child of the root")
+    img = np.empty(P.M, dtype=np.int64)
+    img[0] = ch[0][realized]
+    for n in range(1, P.M):  # stage-sorted: the parent's image is known
+        a = int(P.parent[n])
+        k = ch[a].index(n)
+        kids = ch[int(img[a])]
+        img[n] = kids[min(k, len(kids) - 1)] if kids else img[a]
+    return img
+
+
+def shift_dual(P: OracleProblem, y: np.ndarray, realized: int) -> np.ndarray:
+    """Shifted warm start ``y_new[n] = r_n y[m(n)]`` per block, ``r_n =
+    pi[n] / pi[m(n)]`` for the probability-weighted blocks, 1 otherwise."""
+    img = shift_map(P, realized)
+    nx = P.nx
+    ratio = P.prob / P.prob[img]
+    out = y[img].copy()
+    if P.weight_safety_by_prob:
+        out[:, :nx] *= ratio[:, None]
+    out[:, 2 * nx:] *= ratio[:, None]
+    return out
