@@ -152,8 +152,10 @@ int smpc_tree_info(smpc_tree* tree, int* M, int* N, int* n_chains, int* n_levels
  * the accuracy floor of float32: that tree continues in float64 until the
  * stop test passes or max_iter is reached (stall_checks 0 -> 100, < 0 ->
  * never; not applied when tol = 0).  Reductions are float64 in both modes.
- * warm_start: 0 -> y0 = 0; 2 -> y^0 = y0 and y^{-1} = y_prev0 (or y0 when
- * y_prev0 is NULL), both M*(2nx+nu) in the caller's node order.            */
+ * warm_start: 0 -> y0 = 0; 1 -> y^0 = y^{-1} = the tree's resident dual of
+ * its previous solve, shifted by smpc_shift_warm_start (no host copy);
+ * 2 -> y^0 = y0 and y^{-1} = y_prev0 (or y0 when y_prev0 is NULL), both
+ * M*(2nx+nu) in the caller's node order.                                    */
 typedef struct {
   double tol;
   int max_iter;
@@ -196,6 +198,20 @@ int smpc_solve(smpc_tree* tree, const double* p, const double* q,
 int smpc_solve_batch(smpc_tree* const* trees, int n, const double* const* p,
                      const double* const* q, const smpc_solve_opts* opts,
                      smpc_result* res);
+
+/* Receding-horizon warm start (closed loop of Alg. 2; the paper restarts from
+ * y0 = 0, any dual point is a valid start).  Prepares the next solve of the
+ * same tree with warm_start 1 from the dual the last solve left on the
+ * device.  The next tree's root takes the place of child `realized` of the
+ * root (in the caller's order of the root's children); a deeper node takes
+ * the place of the child of its parent's image with the same child index
+ * (the last child when there are fewer); below the last stage the image
+ * stays (the last stage is repeated).  The safety block (when weighted by
+ * probability) and the input-box block are rescaled by pi_new / pi_old, the
+ * state-box block is kept.  realized = -1 resumes from the dual unshifted.
+ * SMPC_EINVAL without a previous solve (smpc_factor and smpc_solve_step
+ * discard the resident dual) or for a realized index out of range.         */
+int smpc_shift_warm_start(smpc_tree* tree, int realized);
 
 /* Solve step alone (Alg. 1): the primal point z(w) = argmin <z, H'w> + f(z)
  * for a dual point w (M*(2nx+nu), caller's order), i.e. the dual gradient of

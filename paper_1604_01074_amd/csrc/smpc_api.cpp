@@ -506,6 +506,35 @@ int upload_root(smpc_tree* t, const double* p, const double* q) {
   return SMPC_OK;
 }
 
+// Warm start from the resident dual of the previous solve, shifted by the
+// map prepared by smpc_shift_warm_start: y^0 = y^{-1} -> y[0], y[2] of the
+// precision T of the coming phase.
+template <typename Ts, typename Td>
+int shift_resident(smpc_tree* t) {
+  smpc_ctx* ctx = t->sys->ctx;
+  const int nx = t->sys->nx, nu = t->sys->nu, D = 2 * nx + nu, M = t->M;
+  TreeBuffers<Ts>& bs = treebuf<Ts>(t);
+  TreeBuffers<Td>& bd = treebuf<Td>(t);
+  const Ts* src = (const Ts*)bs.y[t->res_slot].ptr;
+  if ((const void*)src == bd.y[0].ptr || (const void*)src == bd.y[2].ptr) {
+    // the gather reads other nodes than it writes: move the source to the
+    // free slot first (slot 1 is overwritten by the first iteration anyway)
+    HIP_TRY(hipMemcpyAsync(bs.y[1].ptr, src, sizeof(Ts) * (size_t)M * D, hipMemcpyDeviceToDevice, ctx->stream));
+    src = (const Ts*)bs.y[1].ptr;
+  }
+  hipError_t (*shift)(const Ts*, Td*, Td*, const int32_t*, const double*, int, int, int, hipStream_t) =
+      launch_shift<Ts, Td>;
+  HIP_TRY(shift(src, (Td*)bd.y[0].ptr, (Td*)bd.y[2].ptr, (const int32_t*)t->shift_src.ptr,
+                (const double*)t->shift_f.ptr, M, nx, nu, ctx->stream));
+  return SMPC_OK;
+}
+
+template <typename Td>
+int start_from_resident(smpc_tree* t) {
+  if (t->res_prec == 32) return shift_resident<float, Td>(t);
+  return shift_resident<double, Td>(t);
+}
+
 // Initial dual iterates (scaled, internal order): y^0 -> y[0], y^{-1} -> y[2].
 template <typename T>
 int upload_dual_start(smpc_tree* t, const double* y0, const double* yprev0) {
@@ -591,7 +620,7 @@ int check_opts(const smpc_solve_opts* o) {
   if (o->precision != 64 && o->precision != 32) return set_error(SMPC_EINVAL, "precision must be 32 or 64");
   if (o->polish_iters < 0 || o->polish_iters > o->max_iter) return set_error(SMPC_EINVAL, "polish_iters out of range");
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return set_error(SMPC_EINVAL, "tol must be finite and >= 0");
-  if (o->warm_start != 0 && o->warm_start != 2) return set_error(SMPC_EINVAL, "warm_start must be 0 or 2");
+  if (o->warm_start < 0 || o->warm_start > 2) return set_error(SMPC_EINVAL, "warm_start must be 0, 1 or 2");
   if (o->warm_start == 2 && !o->y0) return set_error(SMPC_EINVAL, "warm_start 2 needs y0");
   return SMPC_OK;
 }
@@ -623,6 +652,12 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
     size_t off = 0;
     for (int k = 0; k < n; ++k) {
       smpc_tree* t = plan->trees[k];
+      if (o->warm_start == 1) {
+        if (run32) SMPC_TRY(start_from_resident<float>(t));
+        else SMPC_TRY(start_from_resident<double>(t));
+        t->shift_ready = false;
+        continue;
+      }
       const double* y0 = o->warm_start == 2 ? o->y0 + off : nullptr;
       const double* yp0 = (o->warm_start == 2 && o->y_prev0) ? o->y_prev0 + off : nullptr;
       if (run32) SMPC_TRY(upload_dual_start<float>(t, y0, yp0));
@@ -695,6 +730,9 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
     smpc_tree* t = plan->trees[k];
     TreeState h;
     SMPC_TRY(read_state(t, &h));
+    // the final dual y^{nu+1} stays resident for a shifted warm start
+    t->res_slot = h.iters_done % 3;
+    t->res_prec = run64 ? 64 : 32;
     smpc_result* r = res ? &res[k] : nullptr;
     if (!r) continue;
     r->iterations = h.iters_done;
@@ -1053,7 +1091,8 @@ int smpc_tree_destroy(smpc_tree* t) {
   if (t->plan) plan_free(ctx, t->plan);
   tree_free(ctx, t->b64);
   tree_free(ctx, t->b32);
-  DevBuf* extra[] = {&t->cstat, &t->st, &t->chains_dev, &t->cnt, &t->leaves_dev, &t->path_off_dev, &t->path_dev};
+  DevBuf* extra[] = {&t->cstat, &t->st,         &t->chains_dev, &t->cnt,    &t->leaves_dev,
+                     &t->path_off_dev, &t->path_dev, &t->shift_src, &t->shift_f};
   for (DevBuf* b : extra) ctx->release(*b);
   t->sys->n_trees--;
   delete t;
@@ -1088,6 +1127,10 @@ int smpc_tree_set_data(smpc_tree* t, const double* d, const double* alpha2) {
 }
 
 int smpc_factor(smpc_tree* t, const smpc_factor_opts* o) {
+  if (t) {
+    t->res_slot = -1;  // the power iteration overwrites the dual slots
+    t->shift_ready = false;
+  }
   if (!t) return set_error(SMPC_EINVAL, "tree is NULL");
   smpc_factor_opts def{};
   if (!o) o = &def;
@@ -1179,6 +1222,56 @@ int smpc_tree_get_factor(smpc_tree* t, double* lambda, double* scale) {
   return SMPC_OK;
 }
 
+int smpc_shift_warm_start(smpc_tree* t, int realized) {
+  SMPC_TRY(tree_check_ready(t, false));
+  if (t->res_slot < 0) return set_error(SMPC_EINVAL, "no resident dual: solve the tree first");
+  smpc_sys* sys = t->sys;
+  const int M = t->M;
+  // children of every node in the caller's order (stage-sorted input)
+  std::vector<std::vector<int32_t>> ch(M);
+  for (int n = 1; n < M; ++n) ch[t->parent[n]].push_back(n);
+  std::vector<int32_t> img(M);
+  if (realized == -1) {
+    for (int n = 0; n < M; ++n) img[n] = n;  // resume the same tree unshifted
+  } else {
+    if (realized < 0 || realized >= (int)ch[0].size())
+      return set_error(SMPC_EINVAL, "realized child %d out of range (the root has %zu children)", realized,
+                       ch[0].size());
+    // the next root is the realised child; a deeper node follows the child
+    // of its parent's image with its own child index (the last one when there
+    // are fewer); below the last stage the image stays (last stage repeated)
+    img[0] = ch[0][realized];
+    std::vector<int32_t> rank(M, 0);
+    for (int a = 0; a < M; ++a)
+      for (size_t k = 0; k < ch[a].size(); ++k) rank[ch[a][k]] = (int32_t)k;
+    for (int n = 1; n < M; ++n) {
+      const std::vector<int32_t>& kids = ch[img[t->parent[n]]];
+      img[n] = kids.empty() ? img[t->parent[n]] : kids[std::min<size_t>(rank[n], kids.size() - 1)];
+    }
+  }
+  // internal order: source node and per-block factors pi_new / pi_old on the
+  // probability-weighted blocks, times S_old / S_new for the scaled storage
+  std::vector<int32_t> src(M);
+  std::vector<double> f((size_t)M * 3);
+  for (int in = 0; in < M; ++in) {
+    const int n = t->perm[in];
+    const int m = img[n];
+    const int im = t->iperm[m];
+    src[in] = im;
+    const double ratio = t->prob[n] / t->prob[m];
+    for (int b = 0; b < 3; ++b) {
+      const bool weighted = (b == 0 && sys->safety_by_prob) || b == 2;
+      double v = weighted ? ratio : 1.0;
+      if (!t->scale.empty()) v *= t->scale[(size_t)im * 3 + b] / t->scale[(size_t)in * 3 + b];
+      f[(size_t)in * 3 + b] = v;
+    }
+  }
+  SMPC_TRY(upload_i32(sys->ctx, t->shift_src, src));
+  SMPC_TRY(upload<double>(sys->ctx, t->shift_f, f.data(), f.size()));
+  t->shift_ready = true;
+  return SMPC_OK;
+}
+
 int smpc_solve(smpc_tree* t, const double* p, const double* q, const smpc_solve_opts* o, smpc_result* res) {
   SMPC_TRY(tree_check_ready(t, true));
   SMPC_TRY(check_opts(o));
@@ -1189,6 +1282,8 @@ int smpc_solve(smpc_tree* t, const double* p, const double* q, const smpc_solve_
     if (!all_finite(o->y0, n) || (o->y_prev0 && !all_finite(o->y_prev0, n)))
       return set_error(SMPC_ENAN, "NaN or Inf in the warm start");
   }
+  if (o->warm_start == 1 && !t->shift_ready)
+    return set_error(SMPC_EINVAL, "warm_start 1 needs smpc_shift_warm_start after the previous solve");
   const bool need32 = o->precision == 32 && o->max_iter > o->polish_iters;
   if (need32) SMPC_TRY(prepare32(t));
   SMPC_TRY(ensure_single_plan(t, need32));
@@ -1213,6 +1308,8 @@ int smpc_solve_batch(smpc_tree* const* trees, int n, const double* const* p, con
     if (!all_finite(p[k], sys->nx) || !all_finite(q[k], sys->nu)) return set_error(SMPC_ENAN, "NaN or Inf in p/q %d", k);
     for (int j = 0; j < k; ++j)
       if (trees[j] == trees[k]) return set_error(SMPC_EINVAL, "tree %d appears twice in the batch", k);
+    if (o->warm_start == 1 && !trees[k]->shift_ready)
+      return set_error(SMPC_EINVAL, "warm_start 1: tree %d has no prepared shift (smpc_shift_warm_start)", k);
   }
   smpc_ctx* ctx = sys->ctx;
   const bool need32 = o->precision == 32 && o->max_iter > o->polish_iters;
@@ -1241,6 +1338,8 @@ int smpc_solve_batch(smpc_tree* const* trees, int n, const double* const* p, con
 int smpc_solve_step(smpc_tree* t, const double* p, const double* q, const double* w, int precision, double* x,
                     double* u) {
   SMPC_TRY(tree_check_ready(t, false));
+  t->res_slot = -1;  // the solve step overwrites y[0]
+  t->shift_ready = false;
   if (!t->has_data) return set_error(SMPC_ENOTFACTORED, "smpc_tree_set_data not called");
   if (!p || !q || !w) return set_error(SMPC_EINVAL, "NULL argument");
   if (precision != 64 && precision != 32) return set_error(SMPC_EINVAL, "precision must be 32 or 64");

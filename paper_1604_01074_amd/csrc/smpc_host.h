@@ -127,6 +127,12 @@ struct smpc_tree {
   TreeBuffers<float> b32;
   smpc::DevBuf cstat, st, chains_dev, cnt, leaves_dev, path_off_dev, path_dev;
   struct Plan* plan = nullptr;  // single-tree launch plan
+  // resident dual of the last solve (slot of y^{nu+1} and its precision;
+  // -1 when no solve has left one) and a pending warm-start shift
+  int res_slot = -1;
+  int res_prec = 0;
+  bool shift_ready = false;
+  smpc::DevBuf shift_src, shift_f;  // per internal node: source node, 3 factors
 };
 
 // Launch plan: the work lists of one set of trees solved together.

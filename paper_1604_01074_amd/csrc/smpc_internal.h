@@ -125,6 +125,11 @@ hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const W
                           int n_items, const double* ctab, int mode, int32_t* done_out, hipStream_t s);
 template <typename T>
 hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s);
+// Warm-start shift: dst0 = dst2 = f * src gathered by node (per dual block
+// factors f, M x 3, float64); src must not alias dst0 or dst2.
+template <typename Ts, typename Td>
+hipError_t launch_shift(const Ts* src, Td* dst0, Td* dst2, const int32_t* src_node, const double* f, int M,
+                        int nx, int nu, hipStream_t s);
 
 // Row stride of the zero-padded P on the device (and of the staged rho rows).
 __host__ __device__ int p_stride(int nu);

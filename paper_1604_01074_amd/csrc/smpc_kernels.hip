@@ -1026,6 +1026,22 @@ __global__ void k_widen(const T* __restrict__ src, double* __restrict__ dst, siz
   if (i < n) dst[i] = (double)src[i];
 }
 
+// One thread per dual entry of the next tree: the entry of its image node in
+// the previous dual, times the block's factor.
+template <typename Ts, typename Td>
+__global__ void k_shift(const Ts* __restrict__ src, Td* __restrict__ dst0, Td* __restrict__ dst2,
+                        const int32_t* __restrict__ src_node, const double* __restrict__ f, int M, int nx, int nu) {
+  const int D = 2 * nx + nu;
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)M * D) return;
+  const int n = (int)(e / D);
+  const int k = (int)(e - (size_t)n * D);
+  const int b = k < nx ? 0 : (k < 2 * nx ? 1 : 2);
+  const Td v = (Td)(gp(f)[(size_t)n * 3 + b] * (double)gp(src)[(size_t)gp(src_node)[n] * D + k]);
+  gp(dst0)[e] = v;
+  gp(dst2)[e] = v;
+}
+
 // Dynamic LDS above 64 KiB needs an explicit per-kernel opt-in (gfx950 has
 // 160 KiB per CU).
 template <typename K>
@@ -1129,5 +1145,24 @@ template hipError_t launch_forward<double>(const SysDev<double>&, const TreeDev<
 template hipError_t launch_forward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
                                           const double*, int, int32_t*, hipStream_t);
 template hipError_t launch_widen<float>(const float*, double*, size_t, hipStream_t);
+
+template <typename Ts, typename Td>
+hipError_t launch_shift(const Ts* src, Td* dst0, Td* dst2, const int32_t* src_node, const double* f, int M,
+                        int nx, int nu, hipStream_t s) {
+  const size_t n = (size_t)M * (2 * nx + nu);
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL((k_shift<Ts, Td>), dim3(blocks), dim3(256), 0, s, src, dst0, dst2, src_node, f, M, nx, nu);
+  return hipGetLastError();
+}
+
+template hipError_t launch_shift<double, double>(const double*, double*, double*, const int32_t*, const double*,
+                                                 int, int, int, hipStream_t);
+template hipError_t launch_shift<double, float>(const double*, float*, float*, const int32_t*, const double*, int,
+                                                int, int, hipStream_t);
+template hipError_t launch_shift<float, double>(const float*, double*, double*, const int32_t*, const double*, int,
+                                                int, int, hipStream_t);
+template hipError_t launch_shift<float, float>(const float*, float*, float*, const int32_t*, const double*, int,
+                                               int, int, hipStream_t);
 
 }  // namespace smpc

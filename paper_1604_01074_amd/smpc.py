@@ -30,7 +30,7 @@ EXPORTED = [
     "smpc_sys_create", "smpc_sys_destroy",
     "smpc_tree_create", "smpc_tree_destroy", "smpc_tree_set_data",
     "smpc_factor", "smpc_tree_get_factor", "smpc_tree_info",
-    "smpc_solve", "smpc_solve_batch", "smpc_solve_step",
+    "smpc_solve", "smpc_solve_batch", "smpc_shift_warm_start", "smpc_solve_step",
     "smpc_ctx_set_profiling", "smpc_ctx_kernel_stats", "smpc_ctx_reset_stats",
 ]
 
@@ -108,6 +108,7 @@ _sig = {
     "smpc_solve": [_vp, _dp, _dp, C.POINTER(SolveOpts), C.POINTER(Result)],
     "smpc_solve_batch": [C.POINTER(_vp), C.c_int, C.POINTER(_dp), C.POINTER(_dp), C.POINTER(SolveOpts),
                          C.POINTER(Result)],
+    "smpc_shift_warm_start": [_vp, C.c_int],
     "smpc_solve_step": [_vp, _dp, _dp, _dp, C.c_int, _dp, _dp],
     "smpc_ctx_set_profiling": [_vp, C.c_int],
     "smpc_ctx_kernel_stats": [_vp, C.POINTER(KernelStat), C.c_int, _ip],
@@ -234,10 +235,13 @@ def smpc_tree_get_factor(t, with_scale: bool = False):
 
 # ---------------------------------------------------------------- solve
 
-def _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks=0):
+def _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks=0, resident=False):
     keep = [None if y0 is None else _f64(y0), None if y_prev0 is None else _f64(y_prev0)]
+    if resident and y0 is not None:
+        raise ValueError("a resident warm start and y0 exclude each other")
+    warm = 1 if resident else (2 if y0 is not None else 0)
     o = SolveOpts(float(tol), int(max_iter), int(check_every), int(precision), int(polish_iters),
-                  2 if y0 is not None else 0, _ptr(keep[0]), _ptr(keep[1]), int(stall_checks))
+                  warm, _ptr(keep[0]), _ptr(keep[1]), int(stall_checks))
     return o, keep
 
 
@@ -260,11 +264,11 @@ def _finish(r: Result, out: dict) -> dict:
 
 
 def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precision=64, polish_iters=0,
-               y0=None, y_prev0=None, want_x=True, want_y=True, stall_checks=0) -> dict:
+               y0=None, y_prev0=None, want_x=True, want_y=True, stall_checks=0, resident=False) -> dict:
     """``dims = (M, nx, nu)``.  Returns a dict with u0, x, u, y, iterations,
     fp32_iterations, r_primal, hz_t_max, status."""
     M, nx, nu = dims
-    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks)
+    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident)
     r, out = _result(M, nx, nu, want_x, want_y)
     pp, qq = _f64(p), _f64(q)
     _check_solve(_lib.smpc_solve(t, _ptr(pp), _ptr(qq), C.byref(o), C.byref(r)))
@@ -273,9 +277,9 @@ def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precis
 
 def smpc_solve_batch(trees, ps, qs, *, dims_list, tol=1e-3, max_iter=1000, check_every=10, precision=64,
                      polish_iters=0, y0=None, y_prev0=None, want_x=True, want_y=True,
-                     stall_checks=0) -> tuple[int, list]:
+                     stall_checks=0, resident=False) -> tuple[int, list]:
     n = len(trees)
-    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks)
+    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident)
     res = (Result * n)()
     outs = []
     for k, (M, nx, nu) in enumerate(dims_list):
@@ -289,6 +293,10 @@ def smpc_solve_batch(trees, ps, qs, *, dims_list, tol=1e-3, max_iter=1000, check
     tarr = (_vp * n)(*[t.value if isinstance(t, _vp) else t for t in trees])
     code = _check_solve(_lib.smpc_solve_batch(tarr, n, parr, qarr, C.byref(o), res))
     return code, [_finish(res[k], outs[k]) for k in range(n)]
+
+
+def smpc_shift_warm_start(t, realized: int) -> None:
+    _check(_lib.smpc_shift_warm_start(t, int(realized)))
 
 
 def smpc_solve_step(t, p, q, w, *, dims, precision=64):

@@ -100,6 +100,11 @@ class Tree:
     def solve(self, p, q, **kw) -> dict:
         return S.smpc_solve(self.h, p, q, dims=self.dims, **kw)
 
+    def shift_warm_start(self, realized: int) -> None:
+        """Prepare the next solve (``resident=True``) from this tree's last
+        dual, moved one stage forward along root child ``realized``."""
+        S.smpc_shift_warm_start(self.h, realized)
+
     def solve_step(self, p, q, w, precision: int = 64):
         return S.smpc_solve_step(self.h, p, q, w, dims=self.dims, precision=precision)
 
