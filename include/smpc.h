@@ -45,6 +45,7 @@ extern "C" {
 enum {
   SMPC_OK = 0,
   SMPC_MAX_ITER = 1,        /* warning: max_iter reached before tol; outputs valid */
+  SMPC_PENDING = 2,         /* smpc_server_poll: the request has not finished yet  */
   SMPC_EINVAL = -1,         /* bad argument (NULL, negative size, bad flag)        */
   SMPC_EDIM = -2,           /* dimension outside the supported range               */
   SMPC_ENOTSPD = -3,        /* Wu not symmetric positive definite                  */
@@ -182,6 +183,8 @@ typedef struct {
   double r_primal;
   double hz_t_max;
   int status;
+  double queue_ms;  /* server requests: submit -> admission; 0 otherwise */
+  double run_ms;    /* server requests: admission -> result; 0 otherwise  */
 } smpc_result;
 
 /* Solve one tree from initial state p (nx) and previous input q (nu).
@@ -212,6 +215,40 @@ int smpc_solve_batch(smpc_tree* const* trees, int n, const double* const* p,
  * SMPC_EINVAL without a previous solve (smpc_factor and smpc_solve_step
  * discard the resident dual) or for a realized index out of range.         */
 int smpc_shift_warm_start(smpc_tree* tree, int realized);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of closed-loop MPC steps (the loop of Alg. 2 for many
+ * controllers).  A server owns a worker thread that drives the context's
+ * stream.  Queued requests are admitted between iteration blocks; an
+ * admitted request loads its data into its tree, starts its dual (cold, or
+ * from the tree's resident dual shifted as by smpc_shift_warm_start) and
+ * iterates in the launch group of its current precision; each tree leaves as
+ * soon as it stops, so short requests do not wait for long ones.  A result
+ * equals that of smpc_solve on the same tree and inputs bit for bit.
+ * Admission: at most max_active trees iterate at once (0: no limit); a tree
+ * runs one request at a time, in submission order; a request whose float32
+ * buffers do not fit the context's HBM budget waits for another request to
+ * finish.  While a server exists, its system and trees are used only
+ * through the server calls.                                                 */
+typedef struct smpc_server smpc_server;
+typedef struct {
+  smpc_solve_opts solve;  /* tol, max_iter, check_every, precision, polish_iters,
+                             stall_checks; warm_start must be 0 (per request)  */
+  int max_active;
+} smpc_server_opts;
+int smpc_server_create(smpc_sys* sys, const smpc_server_opts* opts, smpc_server** out);
+/* One MPC step for `tree`: d (M*nd) and alpha2 (N*nu) replace the tree's
+ * data as smpc_tree_set_data does (d NULL: keep the data), p and q as in
+ * smpc_solve; warm 0: cold start, 1: resident dual shifted along root child
+ * `realized` (-1: unshifted).  Inputs are copied.  *ticket identifies it.  */
+int smpc_server_submit(smpc_server* srv, smpc_tree* tree, const double* d, const double* alpha2,
+                       const double* p, const double* q, int warm, int realized, uint64_t* ticket);
+/* Wait up to wait_ms (< 0: without limit) for the request; SMPC_PENDING if
+ * it is not done, else its status with res filled (u0 copied when res->u0 is
+ * set; x, u, y must be NULL) and the ticket released.                      */
+int smpc_server_poll(smpc_server* srv, uint64_t ticket, smpc_result* res, int wait_ms);
+/* Finishes the queued and running requests, then stops the worker.         */
+int smpc_server_destroy(smpc_server* srv);
 
 /* Solve step alone (Alg. 1): the primal point z(w) = argmin <z, H'w> + f(z)
  * for a dual point w (M*(2nx+nu), caller's order), i.e. the dual gradient of

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmpc.so")
-SOURCES = ["smpc_kernels.hip", "smpc_setup.cpp", "smpc_api.cpp"]
+SOURCES = ["smpc_kernels.hip", "smpc_setup.cpp", "smpc_api.cpp", "smpc_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -22,6 +22,8 @@ thread_local std::string g_last_error;
 
 namespace smpc {
 
+const char* last_error_text() { return g_last_error.c_str(); }
+
 int set_error(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -34,19 +36,7 @@ int set_error(int code, const char* fmt, ...) {
 
 }  // namespace smpc
 
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess)                                                                  \
-      return set_error(SMPC_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
-                       __FILE__, __LINE__);                                                \
-  } while (0)
 
-#define SMPC_TRY(expr)        \
-  do {                        \
-    int r_ = (expr);          \
-    if (r_ < 0) return r_;    \
-  } while (0)
 
 // ------------------------------------------------------------------ context
 
@@ -130,7 +120,8 @@ void smpc_ctx::flush_profile() {
   prof.clear();
 }
 
-namespace {
+// Library internals (declared in smpc_host.h where other sources use them).
+namespace smpc {
 
 // Bracket one launch with events when profiling is on.
 template <typename F>
@@ -626,6 +617,133 @@ int check_opts(const smpc_solve_opts* o) {
 }
 
 // Solve a set of trees (one plan) with the given options.
+// ---------------------------------------------------------------- per-tree solve steps
+// (shared by the batched solve and the server, so that both run the same
+// arithmetic for a tree)
+
+int stall_limit32(const smpc_solve_opts* o) {
+  // a fixed iteration count (tol = 0) is never cut short
+  return o->tol <= 0.0 || o->stall_checks < 0 ? 0 : (o->stall_checks == 0 ? 100 : o->stall_checks);
+}
+
+int init_tree_state(smpc_tree* t, const smpc_solve_opts* o, int iter, int max_iter, double tol, int stall_limit) {
+  TreeState h{};
+  h.iter = iter;
+  h.done = 0;
+  h.max_iter = max_iter;
+  h.check_every = o->check_every;
+  h.status = 0;
+  h.iters_done = 0;
+  h.tol = tol;
+  h.lambda = t->lambda;
+  h.in_scale = 1.0;
+  h.best_rp = HUGE_VAL;
+  h.stall = 0;
+  h.stall_limit = stall_limit;
+  return write_state(t, h);
+}
+
+SolvePhases phases(const smpc_solve_opts* o) {
+  SolvePhases ph;
+  const bool use32 = o->precision == 32;
+  ph.polish = use32 ? o->polish_iters : 0;
+  ph.max32 = o->max_iter - ph.polish;
+  ph.run32 = use32 && ph.max32 > 0;
+  ph.run64 = !use32 || ph.polish > 0;
+  return ph;
+}
+
+// Root data, dual start (y0 / y_prev0 for warm_start 2, the resident shifted
+// dual for warm_start 1) and the state of the first phase.
+int tree_begin(smpc_tree* t, const double* p, const double* q, const smpc_solve_opts* o, const double* y0,
+               const double* yp0) {
+  const SolvePhases ph = phases(o);
+  SMPC_TRY(upload_root<double>(t, p, q));
+  if (ph.run32) SMPC_TRY(upload_root<float>(t, p, q));
+  if (o->warm_start == 1) {
+    if (ph.run32) SMPC_TRY(start_from_resident<float>(t));
+    else SMPC_TRY(start_from_resident<double>(t));
+    t->shift_ready = false;
+  } else if (ph.run32) {
+    SMPC_TRY(upload_dual_start<float>(t, y0, yp0));
+  } else {
+    SMPC_TRY(upload_dual_start<double>(t, y0, yp0));
+  }
+  if (ph.run32) return init_tree_state(t, o, 0, ph.max32, o->tol, stall_limit32(o));
+  return init_tree_state(t, o, 0, o->max_iter, o->tol, 0);
+}
+
+// After the float32 phase: continue in float64 from the float32 iterates
+// (all three slots) -- polish after the stop test or the float32 budget, run
+// on to the stop test after a stall (status 2), or record the divergence.
+int tree_to_fp64(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int status32) {
+  smpc_ctx* ctx = t->sys->ctx;
+  const SolvePhases ph = phases(o);
+  const int D = 2 * t->sys->nx + t->sys->nu;
+  for (int s = 0; s < 3; ++s)
+    HIP_TRY(launch_widen<float>((const float*)t->b32.y[s].ptr, (double*)t->b64.y[s].ptr, (size_t)t->M * D,
+                                ctx->stream));
+  if (status32 == -9) {
+    SMPC_TRY(init_tree_state(t, o, fp32_iters, fp32_iters, 0.0, 0));
+    TreeState h;
+    SMPC_TRY(read_state(t, &h));
+    h.done = 1;
+    h.status = -9;
+    h.iters_done = fp32_iters;
+    return write_state(t, h);
+  }
+  if (status32 == 2) return init_tree_state(t, o, fp32_iters, o->max_iter, o->tol, 0);
+  return init_tree_state(t, o, fp32_iters, fp32_iters + ph.polish, 0.0, 0);
+}
+
+// Final state of a tree: keep its last dual resident and fill `r` (may be
+// NULL; outputs are downloaded when their pointers are set).
+int tree_result(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int status32, smpc_result* r) {
+  const SolvePhases ph = phases(o);
+  TreeState h;
+  SMPC_TRY(read_state(t, &h));
+  // the final dual y^{nu+1} stays resident for a shifted warm start
+  t->res_slot = h.iters_done % 3;
+  t->res_prec = ph.run64 ? 64 : 32;
+  if (!r) return SMPC_OK;
+  r->iterations = h.iters_done;
+  r->fp32_iterations = ph.run32 ? fp32_iters : 0;
+  r->r_primal = h.r_p;
+  r->hz_t_max = h.hzt;
+  int status;
+  if (h.status == -9 || (ph.run32 && status32 == -9)) status = SMPC_EDIVERGED;
+  else if (ph.run32 && status32 != 2) status = status32 == 0 ? SMPC_OK : SMPC_MAX_ITER;
+  else status = h.status == 0 ? SMPC_OK : SMPC_MAX_ITER;
+  r->status = status;
+  if (ph.run64) {
+    SMPC_TRY(download_primal<double>(t, r->x, r->u, r->u0));
+    if (r->y) SMPC_TRY(download_dual<double>(t, h.iters_done % 3, r->y));
+  } else {
+    SMPC_TRY(download_primal<float>(t, r->x, r->u, r->u0));
+    if (r->y) SMPC_TRY(download_dual<float>(t, h.iters_done % 3, r->y));
+  }
+  return SMPC_OK;
+}
+
+int run_block_prec(smpc_ctx* ctx, smpc_sys* sys, Plan* p, bool fp32, int iters, bool eager) {
+  if (eager) {
+    for (int k = 0; k < iters; ++k) {
+      if (fp32) SMPC_TRY(enqueue_iteration<float>(ctx, sys, p, kModeAPG));
+      else SMPC_TRY(enqueue_iteration<double>(ctx, sys, p, kModeAPG));
+    }
+    return SMPC_OK;
+  }
+  return fp32 ? run_block<float>(ctx, sys, p, kModeAPG, iters) : run_block<double>(ctx, sys, p, kModeAPG, iters);
+}
+
+int read_done(smpc_ctx* ctx, Plan* p) {
+  HIP_TRY(hipMemcpyAsync(p->done_host.data(), p->done.ptr, sizeof(int32_t) * p->trees.size(), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return SMPC_OK;
+}
+
+// Solve a set of trees (one plan) with the given options.
 int solve_plan(Plan* plan, const double* const* p, const double* const* q, const smpc_solve_opts* o,
                smpc_result* res) {
   smpc_sys* sys = plan->trees[0]->sys;
@@ -633,125 +751,29 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
   const int n = (int)plan->trees.size();
   const int D = 2 * sys->nx + sys->nu;
   SMPC_TRY(ctx->ensure_ctab(o->max_iter + 2));
-  const bool use32 = o->precision == 32;
-  const int polish = use32 ? o->polish_iters : 0;
-  const int max32 = o->max_iter - polish;
+  const SolvePhases ph = phases(o);
   const int max_rounds = o->max_iter / o->check_every + 3;
   std::vector<int> fp32_iters(n, 0), status32(n, 0);
-  const bool run32 = use32 && max32 > 0;
-
+  size_t off = 0;
   for (int k = 0; k < n; ++k) {
     smpc_tree* t = plan->trees[k];
-    SMPC_TRY(upload_root<double>(t, p[k], q[k]));
-    if (run32) {
-      SMPC_TRY(upload_root<float>(t, p[k], q[k]));
-    }
+    const double* y0 = o->warm_start == 2 ? o->y0 + off : nullptr;
+    const double* yp0 = (o->warm_start == 2 && o->y_prev0) ? o->y_prev0 + off : nullptr;
+    SMPC_TRY(tree_begin(t, p[k], q[k], o, y0, yp0));
+    off += (size_t)t->M * D;
   }
-  // dual starting points
-  {
-    size_t off = 0;
-    for (int k = 0; k < n; ++k) {
-      smpc_tree* t = plan->trees[k];
-      if (o->warm_start == 1) {
-        if (run32) SMPC_TRY(start_from_resident<float>(t));
-        else SMPC_TRY(start_from_resident<double>(t));
-        t->shift_ready = false;
-        continue;
-      }
-      const double* y0 = o->warm_start == 2 ? o->y0 + off : nullptr;
-      const double* yp0 = (o->warm_start == 2 && o->y_prev0) ? o->y_prev0 + off : nullptr;
-      if (run32) SMPC_TRY(upload_dual_start<float>(t, y0, yp0));
-      else SMPC_TRY(upload_dual_start<double>(t, y0, yp0));
-      off += (size_t)t->M * D;
-    }
-  }
-  auto init_state = [&](smpc_tree* t, int iter, int max_iter, double tol, int stall_limit) {
-    TreeState h{};
-    h.iter = iter;
-    h.done = 0;
-    h.max_iter = max_iter;
-    h.check_every = o->check_every;
-    h.status = 0;
-    h.iters_done = 0;
-    h.tol = tol;
-    h.lambda = t->lambda;
-    h.in_scale = 1.0;
-    h.best_rp = HUGE_VAL;
-    h.stall = 0;
-    h.stall_limit = stall_limit;
-    return write_state(t, h);
-  };
-  // float32 phase: stop at the stop test, at max_iter - polish, or when r_p
-  // has stalled at float32's accuracy floor (status 2)
-  // (a fixed iteration count, tol = 0, is never cut short)
-  const int stall32 = o->tol <= 0.0 || o->stall_checks < 0 ? 0 : (o->stall_checks == 0 ? 100 : o->stall_checks);
-  if (run32) {
-    for (int k = 0; k < n; ++k) SMPC_TRY(init_state(plan->trees[k], 0, max32, o->tol, stall32));
+  if (ph.run32) {
     SMPC_TRY(run_until_done<float>(ctx, sys, plan, o->check_every, max_rounds));
     for (int k = 0; k < n; ++k) {
       TreeState h;
       SMPC_TRY(read_state(plan->trees[k], &h));
       fp32_iters[k] = h.iters_done;
       status32[k] = h.status;
+      if (ph.run64) SMPC_TRY(tree_to_fp64(plan->trees[k], o, fp32_iters[k], status32[k]));
     }
   }
-  const bool run64 = !use32 || polish > 0;
-  if (run64) {
-    for (int k = 0; k < n; ++k) {
-      smpc_tree* t = plan->trees[k];
-      if (run32) {
-        // continue in float64 from the float32 iterates (all three slots)
-        TreeBuffers<float>& b32 = t->b32;
-        TreeBuffers<double>& b64 = t->b64;
-        for (int s = 0; s < 3; ++s)
-          HIP_TRY(launch_widen<float>((const float*)b32.y[s].ptr, (double*)b64.y[s].ptr, (size_t)t->M * D, ctx->stream));
-        if (status32[k] == -9) {
-          SMPC_TRY(init_state(t, fp32_iters[k], fp32_iters[k], 0.0, 0));
-          TreeState h;
-          SMPC_TRY(read_state(t, &h));
-          h.done = 1;
-          h.status = -9;
-          h.iters_done = fp32_iters[k];
-          SMPC_TRY(write_state(t, h));
-        } else if (status32[k] == 2) {
-          // stalled in float32: continue in float64 to the stop test
-          SMPC_TRY(init_state(t, fp32_iters[k], o->max_iter, o->tol, 0));
-        } else {
-          // float32 met the stop test or the float32 budget: polish
-          SMPC_TRY(init_state(t, fp32_iters[k], fp32_iters[k] + polish, 0.0, 0));
-        }
-      } else {
-        SMPC_TRY(init_state(t, 0, o->max_iter, o->tol, 0));
-      }
-    }
-    SMPC_TRY(run_until_done<double>(ctx, sys, plan, o->check_every, max_rounds + polish + 2));
-  }
-  for (int k = 0; k < n; ++k) {
-    smpc_tree* t = plan->trees[k];
-    TreeState h;
-    SMPC_TRY(read_state(t, &h));
-    // the final dual y^{nu+1} stays resident for a shifted warm start
-    t->res_slot = h.iters_done % 3;
-    t->res_prec = run64 ? 64 : 32;
-    smpc_result* r = res ? &res[k] : nullptr;
-    if (!r) continue;
-    r->iterations = h.iters_done;
-    r->fp32_iterations = run32 ? fp32_iters[k] : 0;
-    r->r_primal = h.r_p;
-    r->hz_t_max = h.hzt;
-    int status;
-    if (h.status == -9 || (run32 && status32[k] == -9)) status = SMPC_EDIVERGED;
-    else if (run32 && status32[k] != 2) status = status32[k] == 0 ? SMPC_OK : SMPC_MAX_ITER;
-    else status = h.status == 0 ? SMPC_OK : SMPC_MAX_ITER;
-    r->status = status;
-    if (run64) {
-      SMPC_TRY(download_primal<double>(t, r->x, r->u, r->u0));
-      if (r->y) SMPC_TRY(download_dual<double>(t, h.iters_done % 3, r->y));
-    } else {
-      SMPC_TRY(download_primal<float>(t, r->x, r->u, r->u0));
-      if (r->y) SMPC_TRY(download_dual<float>(t, h.iters_done % 3, r->y));
-    }
-  }
+  if (ph.run64) SMPC_TRY(run_until_done<double>(ctx, sys, plan, o->check_every, max_rounds + ph.polish + 2));
+  for (int k = 0; k < n; ++k) SMPC_TRY(tree_result(plan->trees[k], o, fp32_iters[k], status32[k], res ? &res[k] : nullptr));
   return SMPC_OK;
 }
 
@@ -794,7 +816,7 @@ int prepare32(smpc_tree* t) {
   return SMPC_OK;
 }
 
-}  // namespace
+}  // namespace smpc
 
 // =================================================================== C ABI
 

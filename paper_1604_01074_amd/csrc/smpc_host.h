@@ -16,6 +16,22 @@ namespace smpc {
 
 // ----------------------------------------------------------------- errors
 int set_error(int code, const char* fmt, ...);
+const char* last_error_text();  // this thread's last message
+
+// Propagate a HIP error as SMPC_EDEVICE, or a negative library status.
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return set_error(SMPC_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                       __FILE__, __LINE__);                                                \
+  } while (0)
+
+#define SMPC_TRY(expr)        \
+  do {                        \
+    int r_ = (expr);          \
+    if (r_ < 0) return r_;    \
+  } while (0)
 
 // ----------------------------------------------------------------- dense FP64 helpers
 // Row-major n x n Cholesky (lower factor in place).  False if a pivot is not
@@ -148,6 +164,25 @@ struct Plan {
 };
 
 namespace smpc {
+// smpc_api.cpp: plans and the per-tree solve steps (shared with the server)
+struct SolvePhases {
+  int polish = 0, max32 = 0;
+  bool run32 = false, run64 = false;
+};
+SolvePhases phases(const smpc_solve_opts* o);
+int check_opts(const smpc_solve_opts* o);
+int tree_check_ready(smpc_tree* t, bool need_data);
+int prepare32(smpc_tree* t);
+int plan_build(smpc_ctx* ctx, const std::vector<smpc_tree*>& trees, bool need32, Plan** out);
+void plan_free(smpc_ctx* ctx, Plan* p);
+int tree_begin(smpc_tree* t, const double* p, const double* q, const smpc_solve_opts* o, const double* y0,
+               const double* yp0);
+int tree_to_fp64(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int status32);
+int tree_result(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int status32, smpc_result* r);
+int read_state(smpc_tree* t, TreeState* h);
+int run_block_prec(smpc_ctx* ctx, smpc_sys* sys, Plan* p, bool fp32, int iters, bool eager);
+int read_done(smpc_ctx* ctx, Plan* p);
+
 // smpc_setup.cpp
 int sys_factor(smpc_sys* s);
 void tree_cost_update(smpc_tree* t, const double* d, const double* alpha2);

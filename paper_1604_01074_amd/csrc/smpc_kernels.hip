@@ -527,7 +527,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int nx = sys.nx, nu = sys.nu;
+  const int nu = sys.nu;
 
   // this lane's P entries: P[4 st + lane / 16][16 (wave NT + t) + lane % 16]
   T preg[KS * NT];

@@ -17,10 +17,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsmpc.so")
 
-OK, MAX_ITER = 0, 1
+OK, MAX_ITER, PENDING = 0, 1, 2
 EINVAL, EDIM, ENOTSPD, ERANK, EPROB, ENOMEM, EDEVICE, ENOTFACTORED, EDIVERGED, ENAN = range(-1, -11, -1)
 STATUS_NAMES = {
-    0: "SMPC_OK", 1: "SMPC_MAX_ITER", -1: "SMPC_EINVAL", -2: "SMPC_EDIM", -3: "SMPC_ENOTSPD",
+    0: "SMPC_OK", 1: "SMPC_MAX_ITER", 2: "SMPC_PENDING", -1: "SMPC_EINVAL", -2: "SMPC_EDIM", -3: "SMPC_ENOTSPD",
     -4: "SMPC_ERANK", -5: "SMPC_EPROB", -6: "SMPC_ENOMEM", -7: "SMPC_EDEVICE",
     -8: "SMPC_ENOTFACTORED", -9: "SMPC_EDIVERGED", -10: "SMPC_ENAN",
 }
@@ -32,6 +32,7 @@ EXPORTED = [
     "smpc_factor", "smpc_tree_get_factor", "smpc_tree_info",
     "smpc_solve", "smpc_solve_batch", "smpc_shift_warm_start", "smpc_solve_step",
     "smpc_ctx_set_profiling", "smpc_ctx_kernel_stats", "smpc_ctx_reset_stats",
+    "smpc_server_create", "smpc_server_submit", "smpc_server_poll", "smpc_server_destroy",
 ]
 
 
@@ -85,7 +86,11 @@ class SolveOpts(C.Structure):
 class Result(C.Structure):
     _fields_ = [("u0", _dp), ("x", _dp), ("u", _dp), ("y", _dp), ("iterations", C.c_int),
                 ("fp32_iterations", C.c_int), ("r_primal", C.c_double), ("hz_t_max", C.c_double),
-                ("status", C.c_int)]
+                ("status", C.c_int), ("queue_ms", C.c_double), ("run_ms", C.c_double)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("solve", SolveOpts), ("max_active", C.c_int)]
 
 
 class KernelStat(C.Structure):
@@ -113,6 +118,10 @@ _sig = {
     "smpc_ctx_set_profiling": [_vp, C.c_int],
     "smpc_ctx_kernel_stats": [_vp, C.POINTER(KernelStat), C.c_int, _ip],
     "smpc_ctx_reset_stats": [_vp],
+    "smpc_server_create": [_vp, C.POINTER(ServerOpts), C.POINTER(_vp)],
+    "smpc_server_submit": [_vp, _vp, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.POINTER(C.c_uint64)],
+    "smpc_server_poll": [_vp, C.c_uint64, C.POINTER(Result), C.c_int],
+    "smpc_server_destroy": [_vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -253,7 +262,8 @@ def _result(M, nx, nu, want_x, want_y):
         out["u"] = np.empty((M, nu))
     if want_y:
         out["y"] = np.empty((M, D))
-    r = Result(_ptr(out["u0"]), _ptr(out.get("x")), _ptr(out.get("u")), _ptr(out.get("y")), 0, 0, 0.0, 0.0, 0)
+    r = Result(_ptr(out["u0"]), _ptr(out.get("x")), _ptr(out.get("u")), _ptr(out.get("y")), 0, 0, 0.0, 0.0, 0,
+               0.0, 0.0)
     return r, out
 
 
@@ -324,3 +334,42 @@ def smpc_ctx_kernel_stats(ctx) -> dict:
 
 def smpc_ctx_reset_stats(ctx) -> None:
     _check(_lib.smpc_ctx_reset_stats(ctx))
+
+
+# ---------------------------------------------------------------- serving
+
+def smpc_server_create(sys_handle, *, tol=1e-3, max_iter=1000, check_every=10, precision=32, polish_iters=20,
+                       stall_checks=0, max_active=0):
+    o, _ = _opts(tol, max_iter, check_every, precision, polish_iters, None, None, stall_checks)
+    so = ServerOpts(o, int(max_active))
+    h = _vp()
+    _check(_lib.smpc_server_create(sys_handle, C.byref(so), C.byref(h)))
+    return h
+
+
+def smpc_server_submit(srv, tree, p, q, *, d=None, alpha2=None, warm=0, realized=0) -> int:
+    pp, qq = _f64(p), _f64(q)
+    dd = None if d is None else _f64(d)
+    aa = None if alpha2 is None else _f64(alpha2)
+    tk = C.c_uint64()
+    _check(_lib.smpc_server_submit(srv, tree, _ptr(dd), _ptr(aa), _ptr(pp), _ptr(qq), int(warm), int(realized),
+                                   C.byref(tk)))
+    return tk.value
+
+
+def smpc_server_poll(srv, ticket: int, nu: int, wait_ms: int = -1):
+    """None while the request runs, else a dict with u0, iterations,
+    fp32_iterations, r_primal, hz_t_max, status, queue_ms, run_ms."""
+    u0 = np.empty(nu)
+    r = Result(_ptr(u0), None, None, None, 0, 0, 0.0, 0.0, 0, 0.0, 0.0)
+    code = _lib.smpc_server_poll(srv, C.c_uint64(ticket), C.byref(r), int(wait_ms))
+    if code == PENDING:
+        return None
+    if code < 0 and code != EDIVERGED:
+        raise SmpcError(code, last_error())
+    return dict(u0=u0, iterations=r.iterations, fp32_iterations=r.fp32_iterations, r_primal=r.r_primal,
+                hz_t_max=r.hz_t_max, status=r.status, queue_ms=r.queue_ms, run_ms=r.run_ms)
+
+
+def smpc_server_destroy(srv) -> None:
+    _check(_lib.smpc_server_destroy(srv))

@@ -65,6 +65,11 @@ class System:
     def solve_batch(self, trees, ps, qs, **kw):
         return S.smpc_solve_batch([t.h for t in trees], ps, qs, dims_list=[t.dims for t in trees], **kw)
 
+    def server(self, **kw) -> "Server":
+        """Continuous-batching server over this system's trees (see
+        smpc_server_create); close it before using the trees directly."""
+        return Server(self, **kw)
+
     def close(self) -> None:
         for t in self.trees:
             t.close()
@@ -122,3 +127,20 @@ def from_instance(ctx: Context, inst, system: System | None = None, **factor_kw)
     t.set_data(inst.d, inst.alpha2)
     t.factor(**factor_kw)
     return system, t
+
+
+class Server:
+    def __init__(self, system: System, **kw):
+        self.system = system
+        self.h = S.smpc_server_create(system.h, **kw)
+
+    def submit(self, tree: Tree, p, q, *, d=None, alpha2=None, warm: int = 0, realized: int = 0) -> int:
+        return S.smpc_server_submit(self.h, tree.h, p, q, d=d, alpha2=alpha2, warm=warm, realized=realized)
+
+    def poll(self, ticket: int, wait_ms: int = -1):
+        return S.smpc_server_poll(self.h, ticket, self.system.nu, wait_ms)
+
+    def close(self) -> None:
+        if self.h is not None:
+            S.smpc_server_destroy(self.h)
+            self.h = None
