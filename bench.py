@@ -117,6 +117,12 @@ def main() -> int:
     ap.add_argument("--max-iter", type=int, default=50000, help="iteration cap of the float64 solves")
     ap.add_argument("--batch-max-iter", type=int, default=30000, help="iteration cap of the batched solves")
     ap.add_argument("--only-batch", action="store_true", help="run only the batched FP32 leg (profiling aid)")
+    ap.add_argument("--serve-requests", type=int, default=100, help="requests of the served closed loop (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrival rate of the served loop, req/s")
+    ap.add_argument("--serve-controllers", type=int, default=256)
+    ap.add_argument("--serve-max-iter", type=int, default=20000)
+    ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--only-serve", action="store_true", help="run only the served closed loop")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device a few times (scales HBM byte counters)")
     a = ap.parse_args()
@@ -141,6 +147,12 @@ def main() -> int:
         print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
                           "launches": 5}), flush=True)
         return 0
+    if a.only_serve:
+        ctx = solver.Context(0)
+        print(json.dumps({"serving": serving_leg(ctx, a.serve_controllers, a.serve_requests, a.serve_rate,
+                                                  a.serve_max_iter, a.serve_max_active)}), flush=True)
+        ctx.close()
+        return 0
     if a.only_batch:
         ctx = solver.Context(0)
         print(json.dumps({"batched_fp32": batched_leg(ctx, a.batch_steps, a.batch_max_iter)}), flush=True)
@@ -149,7 +161,7 @@ def main() -> int:
     inst = ds.barcelona_instance()
     nx, nu = inst.sys["nx"], inst.sys["nu"]
     ctx = solver.Context(0)
-    system, tree = solver.from_instance(ctx, inst, precond=1, power_iters=200)
+    system, tree = solver.from_instance(ctx, inst, precond=2, power_iters=200)
     lam, S = tree.factor_info(with_scale=True)
     info = tree.info()
     opts = dict(tol=1e-3, max_iter=a.max_iter, check_every=10, precision=64, want_x=False, want_y=False)
@@ -210,7 +222,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": "Barcelona-shaped plain method, FP64: nx=63 nu=114 nd=88 ne=17, N=24, "
                                "branching [7,7,7] (343 scenarios, 7260 nodes), tol 1e-3, cold start",
-                   "nodes": inst.M, "tol": 1e-3, "check_every": 10, "precond": "single-branch diagonal"},
+                   "nodes": inst.M, "tol": 1e-3, "check_every": 10,
+                   "precond": "single-branch block diagonal to the power -1/4"},
         "solves_per_s": round(sum(conv) / elapsed, 3),
         "solves_reaching_tol": int(sum(conv)),
         "r_primal_at_exit": r["r_primal"],
@@ -227,11 +240,99 @@ def main() -> int:
     if not a.no_batch:
         out["batched_fp32"] = batched_leg(ctx, a.batch_steps, a.batch_max_iter)
 
+    if a.serve_requests > 0:
+        out["serving"] = serving_leg(ctx, a.serve_controllers, a.serve_requests, a.serve_rate, a.serve_max_iter,
+                                     a.serve_max_active)
+
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds, S, lam)
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0
+
+
+def serving_leg(ctx, n_ctrl: int, n_req: int, rate: float, max_iter: int, max_active: int,
+                seed: int = 2024) -> dict:
+    """Served closed loop: ``n_ctrl`` controllers (tree sizes as in the batch)
+    issue MPC steps at Poisson times (total rate ``rate``); a controller's
+    next step waits for its previous control, its plant advances by
+    ``x+ = A x + B u0 + Gd d0`` (d0: the realised root demand, levels clipped
+    to the box) and it starts warm from its shifted resident dual along a
+    random realised root child.  Latency = queue + run time measured by the
+    library; solves/s = completed requests over the loop's wall time."""
+    import dwn_synth as ds
+
+    insts = ds.serving_controllers(n_ctrl, seed)
+    sysd = insts[0].sys
+    system = ctx.system(sysd)
+    t0 = time.perf_counter()
+    trees = []
+    for k, inst in enumerate(insts):
+        t = system.tree(inst.tree)
+        t.set_data(inst.d, inst.alpha2)
+        t.factor(precond=2, power_iters=50)
+        trees.append(t)
+        if k % 64 == 63:
+            print(f"[bench] serving setup {k + 1}/{len(insts)}", file=sys.stderr, flush=True)
+    setup_s = time.perf_counter() - t0
+    nodes = sum(i.M for i in insts)
+    A, B, Gd = (np.asarray(sysd[k]) for k in ("A", "B", "Gd"))
+    lo, hi = np.asarray(sysd["xmin"]), np.asarray(sysd["xmax"])
+    rng = np.random.default_rng([seed, 1])
+    x = [i.p.copy() for i in insts]
+    q = [i.q.copy() for i in insts]
+    step = [0] * n_ctrl
+    last_d = [None] * n_ctrl
+    busy = [None] * n_ctrl
+    nxt = list(rng.exponential(n_ctrl / rate, n_ctrl))  # each controller: Poisson at rate / n_ctrl
+    srv = system.server(tol=1e-3, max_iter=max_iter, check_every=10, precision=32, polish_iters=20,
+                        max_active=max_active)
+    done, lat, cold_it, warm_it, reached, submitted = [], [], [], [], 0, 0
+    start = time.perf_counter()
+    try:
+        while len(done) < n_req:
+            now = time.perf_counter() - start
+            for c in range(n_ctrl):
+                if busy[c] is None and nxt[c] <= now and submitted < n_req:
+                    d, a2 = ds.step_demands(insts[c], step[c], rng)
+                    nroot = int(np.sum(np.asarray(insts[c].tree["parent"]) == 0))
+                    warm = 1 if step[c] > 0 else 0
+                    busy[c] = srv.submit(trees[c], x[c], q[c], d=d, alpha2=a2, warm=warm,
+                                         realized=int(rng.integers(max(nroot, 1))) if nroot else -1)
+                    last_d[c] = d
+                    submitted += 1
+            for c in range(n_ctrl):
+                if busy[c] is None:
+                    continue
+                r = srv.poll(busy[c], wait_ms=0)
+                if r is None:
+                    continue
+                busy[c] = None
+                done.append(r)
+                lat.append(r["queue_ms"] + r["run_ms"])
+                (warm_it if step[c] > 0 else cold_it).append(r["iterations"])
+                reached += int(r["status"] == 0)
+                u0 = r["u0"]
+                x[c] = np.clip(A @ x[c] + B @ u0 + Gd @ last_d[c][0], lo, hi)
+                q[c] = u0
+                step[c] += 1
+                nxt[c] = max(nxt[c], time.perf_counter() - start) + rng.exponential(n_ctrl / rate)
+            time.sleep(0.0002)
+            if len(done) and len(done) % 100 == 0 and len(done) != getattr(serving_leg, "_last", -1):
+                serving_leg._last = len(done)
+                print(f"[bench] serving {len(done)}/{n_req} done", file=sys.stderr, flush=True)
+    finally:
+        srv.close()
+    wall = time.perf_counter() - start
+    system.close()
+    ctx.systems.remove(system)
+    return {"controllers": n_ctrl, "nodes": nodes, "requests": len(done), "arrival_rate_per_s": rate,
+            "max_active": max_active, "wall_s": round(wall, 2), "solves_per_s": round(len(done) / wall, 2),
+            "reached_tol": reached,
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2), "p99": round(float(np.percentile(lat, 99)), 2)},
+            "iterations_cold_median": float(np.median(cold_it)) if cold_it else None,
+            "iterations_warm_median": float(np.median(warm_it)) if warm_it else None,
+            "setup_s": round(setup_s, 2), "dtype": "f32 bulk, f64 finish after a stall, 20 f64 polish"}
 
 
 def batched_leg(ctx, steps: int, max_iter: int) -> dict:
@@ -246,7 +347,7 @@ def batched_leg(ctx, steps: int, max_iter: int) -> dict:
     for k, inst in enumerate(insts):
         t = system.tree(inst.tree)
         t.set_data(inst.d, inst.alpha2)
-        t.factor(precond=1, power_iters=100)
+        t.factor(precond=2, power_iters=100)
         trees.append(t)
         if k % 16 == 15:
             print(f"[bench] batch setup {k + 1}/{len(insts)}", file=sys.stderr, flush=True)

@@ -17,6 +17,8 @@ from .instances import (
     batch_instances,
     random_small_instance,
     barcelona_demands,
+    serving_controllers,
+    step_demands,
 )
 
 __all__ = [
@@ -33,4 +35,6 @@ __all__ = [
     "batch_instances",
     "random_small_instance",
     "barcelona_demands",
+    "serving_controllers",
+    "step_demands",
 ]

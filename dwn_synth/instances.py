@@ -15,6 +15,10 @@ Workload recipes (all seeded, all synthetic):
   system, horizons in {12, 18, 24}, scenario counts in {16, 64, 125, 343, 512}.
 * ``random_small_instance``: small dense systems with general ``A`` and
   couplings, for exact-arithmetic checks.
+* ``serving_controllers``: 256 controllers on the shared Barcelona-shaped
+  system, tree sizes drawn as for the batch (seed 2024), for the served
+  closed loop; ``step_demands`` draws a controller's demands for a later
+  hour (shifted profile, fresh per-node noise).
 """
 
 from __future__ import annotations
@@ -155,3 +159,31 @@ def random_small_instance(seed: int, nx: int = 4, nu: int = 5, nd: int = 3, ne: 
     p = rng.uniform(0.0, 2.0, nx)
     q = rng.uniform(-1.0, 1.0, nu)
     return Instance(f"random{seed}", sys, tree, d, alpha2, p, q)
+
+
+def serving_controllers(n: int = 256, seed: int = 2024, system_seed: int = 1) -> list[Instance]:
+    """``n`` controllers for the served closed loop: controller ``i`` draws its
+    horizon, scenario count and initial levels like a batch tree, from
+    ``default_rng([seed, i])``, on the shared Barcelona-shaped system."""
+    sys = barcelona_shaped_system(system_seed)
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng([seed, i])
+        N = int(rng.choice(BATCH_HORIZONS))
+        scen = int(rng.choice(sorted(BATCH_SHAPES)))
+        tree = uniform_tree(N, BATCH_SHAPES[scen])
+        d, uf = barcelona_demands(sys, tree, rng)
+        p = sys["xmax"] * rng.uniform(0.4, 0.8, sys["nx"])
+        q = 0.3 * sys["umax"]
+        out.append(Instance(f"ctrl{i}-N{N}-s{scen}", sys, tree, d, pumping_cost(sys, N), p, q,
+                            extra={"uf": uf, "seed": [seed, i]}))
+    return out
+
+
+def step_demands(inst: Instance, step: int, rng: np.random.Generator) -> tuple[np.ndarray, np.ndarray]:
+    """Demands and pumping cost of ``inst``'s tree for the MPC step ``step``
+    hours later: the same per-demand profiles shifted by ``step`` hours, with
+    fresh node noise."""
+    sys, tree = inst.sys, inst.tree
+    d, _ = barcelona_demands(sys, tree, rng, start_hour=step)
+    return d, pumping_cost(sys, int(tree["N"]), start_hour=step)

@@ -1169,19 +1169,22 @@ int smpc_factor(smpc_tree* t, const smpc_factor_opts* o) {
         if (!(v > 0.0)) return set_error(SMPC_EINVAL, "scale must be positive");
         t->scale[(size_t)t->iperm[n] * 3 + b] = v;
       }
-  } else if (o->precond == 1) {
+  } else if (o->precond == 1 || o->precond == 2) {
+    // the per-node block diagonal of the dual Hessian (single-branch model,
+    // divided by pi_n) to the power -1/2 (1) or -1/4 (2)
     std::vector<double> diag;
     single_branch_precond(s, t->N, diag);
     t->scale.assign((size_t)M * 3, 1.0);
     for (int n = 0; n < M; ++n)
       for (int b = 0; b < 3; ++b) {
         const double dd = diag[(size_t)t->stage[n] * 3 + b];
-        t->scale[(size_t)t->iperm[n] * 3 + b] = dd > 0.0 ? std::sqrt(t->prob[n] / dd) : 1.0;
+        const double v = dd > 0.0 ? std::sqrt(t->prob[n] / dd) : 1.0;
+        t->scale[(size_t)t->iperm[n] * 3 + b] = o->precond == 1 ? v : std::sqrt(v);
       }
   } else if (o->precond == 0) {
     t->scale.clear();
   } else {
-    return set_error(SMPC_EINVAL, "precond must be 0 or 1");
+    return set_error(SMPC_EINVAL, "precond must be 0, 1 or 2");
   }
   SMPC_TRY(tree_upload_scale<double>(t));
   SMPC_TRY(tree_alloc<double>(t));
