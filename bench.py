@@ -123,6 +123,8 @@ def main() -> int:
     ap.add_argument("--serve-max-iter", type=int, default=20000)
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--only-serve", action="store_true", help="run only the served closed loop")
+    ap.add_argument("--chunk64", default="", metavar="BWD,FWD",
+                    help="fixed float64 chunk lengths of the plain leg instead of tuning them (counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device a few times (scales HBM byte counters)")
     a = ap.parse_args()
@@ -164,7 +166,11 @@ def main() -> int:
     system, tree = solver.from_instance(ctx, inst, precond=2, power_iters=200)
     lam, S = tree.factor_info(with_scale=True)
     info = tree.info()
-    opts = dict(tol=1e-3, max_iter=a.max_iter, check_every=10, precision=64, want_x=False, want_y=False)
+    # tune 1: the warm-up solve times every chunk-length pair on its first
+    # blocks and the tree's plan keeps the fastest
+    opts = dict(tol=1e-3, max_iter=a.max_iter, check_every=10, precision=64, want_x=False, want_y=False, tune=1)
+    if a.chunk64:
+        opts.update(tune=0, chunk64=tuple(int(v) for v in a.chunk64.split(",")))
     print(f"[bench] plain FP64: M={inst.M} chains={info['n_chains']} levels={info['n_levels']} lambda={lam:.4e}",
           file=sys.stderr, flush=True)
     for _ in range(a.warmup):
@@ -199,9 +205,10 @@ def main() -> int:
     nodes_per_launch = inst.M
     per_node = node_bytes(dom, nx, nu, 8, True)
     achieved = per_node * nodes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom)
+    chunk = r["chunk64"][0 if dom.startswith("backward") else 1]
+    traffic = measured_traffic(f"{dom} chunk {chunk}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom, "chunk": chunk,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": per_node * nodes_per_launch}
     kernels = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["total_ms"] / v["launches"], 2),
                    "share": round(v["total_ms"] / sum(x["total_ms"] for x in stats.values()), 3)}
@@ -223,7 +230,8 @@ def main() -> int:
         "config": {"workload": "Barcelona-shaped plain method, FP64: nx=63 nu=114 nd=88 ne=17, N=24, "
                                "branching [7,7,7] (343 scenarios, 7260 nodes), tol 1e-3, cold start",
                    "nodes": inst.M, "tol": 1e-3, "check_every": 10,
-                   "precond": "single-branch block diagonal to the power -1/4"},
+                   "precond": "single-branch block diagonal to the power -1/4",
+                   "chunks_fp64": list(r["chunk64"])},
         "solves_per_s": round(sum(conv) / elapsed, 3),
         "solves_reaching_tol": int(sum(conv)),
         "r_primal_at_exit": r["r_primal"],
@@ -354,7 +362,7 @@ def batched_leg(ctx, steps: int, max_iter: int) -> dict:
     setup_s = time.perf_counter() - t0
     nodes = sum(i.M for i in insts)
     kw = dict(tol=1e-3, max_iter=max_iter, check_every=10, precision=32, polish_iters=20, stall_checks=100,
-              want_x=False, want_y=False)
+              want_x=False, want_y=False, tune=1)
     ps = [i.p for i in insts]
     qs = [i.q for i in insts]
     print(f"[bench] batch: {len(trees)} trees, {nodes} nodes, setup {setup_s:.1f} s", file=sys.stderr, flush=True)
@@ -381,6 +389,7 @@ def batched_leg(ctx, steps: int, max_iter: int) -> dict:
            "iterations_median": float(np.median([r["iterations"] for r in res])),
            "fp32_iterations_median": float(np.median([r["fp32_iterations"] for r in res])),
            "max_iter": max_iter, "status_worst": int(code), "setup_s": round(setup_s, 2),
+           "chunks_fp32": list(res[0]["chunk32"]), "chunks_fp64": list(res[0]["chunk64"]),
            "dtype": "f32 bulk, f64 finish after a float32 stall (100 checks), 20 f64 polish"}
     system.close()
     ctx.systems.remove(system)

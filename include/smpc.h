@@ -159,7 +159,20 @@ int smpc_tree_info(smpc_tree* tree, int* M, int* N, int* n_chains, int* n_levels
  * warm_start: 0 -> y0 = 0; 1 -> y^0 = y^{-1} = the tree's resident dual of
  * its previous solve, shifted by smpc_shift_warm_start (no host copy);
  * 2 -> y^0 = y0 and y^{-1} = y_prev0 (or y0 when y_prev0 is NULL), both
- * M*(2nx+nu) in the caller's node order.                                    */
+ * M*(2nx+nu) in the caller's node order.
+ * Chunk lengths (nodes a kernel stages between barriers; a launch-shape
+ * choice that never changes the result, which is bit-identical for every
+ * length): chunk32 / chunk64 = {backward, forward} lengths for the float32 /
+ * float64 iterations, each 0 or a length smpc_chunk_lengths lists.  A
+ * precision with a nonzero entry uses exactly those lengths (0 -> the
+ * default).  Otherwise tune 0 uses the defaults, and tune 1 uses the lengths
+ * an earlier tuned solve of the same launch plan (the tree, or the same set
+ * of trees in smpc_solve_batch) chose, or, if none has, times every listed
+ * pair on the first iteration blocks of this solve (two timed blocks each,
+ * after one that warms the pair up; these are ordinary iterations of the
+ * solve) and keeps the fastest for the plan and as the system's choice for
+ * servers.  A solve whose trees all stop before every pair is timed leaves
+ * the plan untuned.                                                        */
 typedef struct {
   double tol;
   int max_iter;
@@ -170,7 +183,15 @@ typedef struct {
   const double* y0;
   const double* y_prev0;
   int stall_checks;
+  int tune;
+  int chunk32[2];
+  int chunk64[2];
 } smpc_solve_opts;
+
+/* Chunk lengths built into the library for `precision` (32 or 64) and
+ * kernel `which` (0 backward, 1 forward), default first: up to cap entries
+ * are written to out and their number to *n.                               */
+int smpc_chunk_lengths(int precision, int which, int* out, int cap, int* n);
 
 /* Caller-allocated outputs; any pointer may be NULL.  u0: nu, x: M*nx,
  * u: M*nu (last primal iterate z^nu), y: M*(2nx+nu) (y^{nu+1}).
@@ -188,6 +209,8 @@ typedef struct {
   int status;
   double queue_ms;  /* server requests: submit -> admission; 0 otherwise */
   double run_ms;    /* server requests: admission -> result; 0 otherwise  */
+  int chunk32[2];   /* {backward, forward} chunk lengths the float32 / float64 */
+  int chunk64[2];   /* iterations ended with; {0, 0} for a precision not run  */
 } smpc_result;
 
 /* Solve one tree from initial state p (nx) and previous input q (nu).
@@ -236,7 +259,10 @@ int smpc_shift_warm_start(smpc_tree* tree, int realized);
 typedef struct smpc_server smpc_server;
 typedef struct {
   smpc_solve_opts solve;  /* tol, max_iter, check_every, precision, polish_iters,
-                             stall_checks; warm_start must be 0 (per request)  */
+                             stall_checks, chunk32, chunk64 (tune 1: the
+                             system's tuned lengths where it has them; the
+                             server itself does not time); warm_start must be
+                             0 (per request)                                  */
   int max_active;
 } smpc_server_opts;
 int smpc_server_create(smpc_sys* sys, const smpc_server_opts* opts, smpc_server** out);

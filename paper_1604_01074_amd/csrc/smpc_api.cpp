@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <iterator>
 #include <new>
 #include <string>
 #include <vector>
@@ -376,6 +377,10 @@ int plan_build(smpc_ctx* ctx, const std::vector<smpc_tree*>& trees, bool need32,
   }
   p->done_host.assign(trees.size(), 0);
   p->has32 = need32;
+  p->chunk[0][0] = Chunks<double>::bwd[0];
+  p->chunk[0][1] = Chunks<double>::fwd[0];
+  p->chunk[1][0] = Chunks<float>::bwd[0];
+  p->chunk[1][1] = Chunks<float>::fwd[0];
   *out = p;
   return SMPC_OK;
 }
@@ -386,6 +391,12 @@ template <>
 const TreeDev<double>* plan_td<double>(Plan* p) { return (const TreeDev<double>*)p->td64.ptr; }
 template <>
 const TreeDev<float>* plan_td<float>(Plan* p) { return (const TreeDev<float>*)p->td32.ptr; }
+
+// Index of a precision in the per-plan chunk tables: 0 float64, 1 float32.
+template <typename T>
+constexpr int pix() {
+  return sizeof(T) == 4 ? 1 : 0;
+}
 
 template <typename T>
 const char* kname(int which);
@@ -407,15 +418,17 @@ int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode) {
   const TreeDev<T>* td = plan_td<T>(p);
   const WorkItem* items = (const WorkItem*)p->items.ptr;
   hipStream_t s = ctx->stream;
-  HIP_TRY(timed(ctx, kname<T>(0), [&] { return launch_backward<T>(sv, td, items, p->n_items, ctx->ctab, mode, s); }));
+  const int* ch = p->chunk[pix<T>()];
+  HIP_TRY(timed(ctx, kname<T>(0),
+                [&] { return launch_backward<T>(sv, td, items, p->n_items, ctx->ctab, mode, ch[0], s); }));
   HIP_TRY(timed(ctx, kname<T>(1), [&] {
-    return launch_forward<T>(sv, td, items, p->n_items, ctx->ctab, mode, (int32_t*)p->done.ptr, s);
+    return launch_forward<T>(sv, td, items, p->n_items, ctx->ctab, mode, ch[1], (int32_t*)p->done.ptr, s);
   }));
   return SMPC_OK;
 }
 
 // Enqueue `iters` iterations.  Without profiling they are captured once into a
-// hipGraph per (precision, mode, iters) and replayed: the kernels take every
+// hipGraph per (precision, mode, iters, chunk lengths) and replayed: the kernels take every
 // per-iteration quantity from the device-side tree state, so one graph serves
 // every block of a solve.
 template <typename T>
@@ -428,7 +441,8 @@ int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
     plan_drop_graphs(p);
     p->graphs_ctab_gen = ctx->ctab_gen;
   }
-  const auto key = std::make_tuple((int)sizeof(T), mode, iters);
+  const int* ch = p->chunk[pix<T>()];
+  const auto key = std::make_tuple((int)sizeof(T), mode, iters, ch[0], ch[1]);
   auto found = p->graphs.find(key);
   if (found == p->graphs.end()) {
     HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
@@ -451,18 +465,98 @@ int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
   return SMPC_OK;
 }
 
-// Run APG iterations until every tree of the plan is done.
+bool plan_all_done(const Plan* p) {
+  for (int32_t d : p->done_host)
+    if (!d) return false;
+  return true;
+}
+
+int read_done(smpc_ctx* ctx, Plan* p) {
+  HIP_TRY(hipMemcpyAsync(p->done_host.data(), p->done.ptr, sizeof(int32_t) * p->trees.size(), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return SMPC_OK;
+}
+
+// Chunk-length autotuner: run the plan's next APG blocks with each listed
+// (backward, forward) pair in turn -- one block to instantiate its graph and
+// load its code, then two timed blocks -- and keep the pair with the
+// shortest block.  The blocks are iterations of the running solve (the chunk
+// length does not change the iterates).  Consumes up to 3 x pairs blocks of
+// `rounds`; leaves the plan untuned when every tree stops first.
 template <typename T>
-int run_until_done(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int check_every, int max_rounds) {
-  for (int round = 0; round < max_rounds; ++round) {
-    SMPC_TRY(run_block<T>(ctx, sys, p, kModeAPG, check_every));
-    HIP_TRY(hipMemcpyAsync(p->done_host.data(), p->done.ptr, sizeof(int32_t) * p->trees.size(),
-                           hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    bool all = true;
-    for (int32_t d : p->done_host) all = all && d;
-    if (all) return SMPC_OK;
+int tune_chunks(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int iters, int max_rounds, int& rounds) {
+  int* ch = p->chunk[pix<T>()];
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  HIP_TRY(hipEventCreate(&ev[0]));
+  hipError_t e = hipEventCreate(&ev[1]);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return set_error(SMPC_EDEVICE, "event creation failed: %s", hipGetErrorString(e));
   }
+  int rc = SMPC_OK;
+  float best = HUGE_VALF;
+  int best_b = ch[0], best_f = ch[1];
+  bool complete = true;
+  for (int b : Chunks<T>::bwd) {
+    for (int f : Chunks<T>::fwd) {
+      ch[0] = b;
+      ch[1] = f;
+      float ms = HUGE_VALF;
+      for (int rep = 0; rep < 3 && complete && rc >= 0; ++rep) {
+        if (rounds >= max_rounds || plan_all_done(p)) {
+          complete = false;
+          break;
+        }
+        const bool timed_block = rep > 0;
+        if (timed_block) e = hipEventRecord(ev[0], ctx->stream);
+        if (e == hipSuccess) rc = run_block<T>(ctx, sys, p, kModeAPG, iters);
+        if (rc >= 0 && timed_block && e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+        if (rc >= 0 && e == hipSuccess) rc = read_done(ctx, p);
+        if (rc >= 0 && timed_block && e == hipSuccess) {
+          float t = 0.f;
+          e = hipEventElapsedTime(&t, ev[0], ev[1]);
+          ms = std::min(ms, t);
+        }
+        if (e != hipSuccess && rc >= 0) rc = set_error(SMPC_EDEVICE, "autotune timing failed: %s", hipGetErrorString(e));
+        ++rounds;
+      }
+      if (!complete || rc < 0) break;
+      if (ms < best) {
+        best = ms;
+        best_b = b;
+        best_f = f;
+      }
+    }
+    if (!complete || rc < 0) break;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  SMPC_TRY(rc);
+  ch[0] = best_b;
+  ch[1] = best_f;
+  if (complete) {
+    p->tuned[pix<T>()] = true;
+    sys->tuned_chunk[pix<T>()][0] = best_b;
+    sys->tuned_chunk[pix<T>()][1] = best_f;
+    sys->has_tuned[pix<T>()] = true;
+  }
+  return SMPC_OK;
+}
+
+// Run APG iterations until every tree of the plan is done (after tuning the
+// chunk lengths first when `tune` is set and the plan has no tuned pair).
+template <typename T>
+int run_until_done(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int check_every, int max_rounds, bool tune) {
+  int round = 0;
+  std::fill(p->done_host.begin(), p->done_host.end(), 0);
+  if (tune && !p->tuned[pix<T>()]) SMPC_TRY(tune_chunks<T>(ctx, sys, p, check_every, max_rounds, round));
+  for (; round < max_rounds; ++round) {
+    if (plan_all_done(p)) return SMPC_OK;
+    SMPC_TRY(run_block<T>(ctx, sys, p, kModeAPG, check_every));
+    SMPC_TRY(read_done(ctx, p));
+  }
+  if (plan_all_done(p)) return SMPC_OK;
   return set_error(SMPC_EDEVICE, "iteration driver did not terminate");
 }
 
@@ -613,6 +707,15 @@ int check_opts(const smpc_solve_opts* o) {
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return set_error(SMPC_EINVAL, "tol must be finite and >= 0");
   if (o->warm_start < 0 || o->warm_start > 2) return set_error(SMPC_EINVAL, "warm_start must be 0, 1 or 2");
   if (o->warm_start == 2 && !o->y0) return set_error(SMPC_EINVAL, "warm_start 2 needs y0");
+  if (o->tune != 0 && o->tune != 1) return set_error(SMPC_EINVAL, "tune must be 0 or 1");
+  for (int w = 0; w < 2; ++w) {
+    if (o->chunk32[w] != 0 && !(w == 0 ? chunk_listed(Chunks<float>::bwd, o->chunk32[w])
+                                       : chunk_listed(Chunks<float>::fwd, o->chunk32[w])))
+      return set_error(SMPC_EINVAL, "chunk32[%d] = %d is not a built chunk length", w, o->chunk32[w]);
+    if (o->chunk64[w] != 0 && !(w == 0 ? chunk_listed(Chunks<double>::bwd, o->chunk64[w])
+                                       : chunk_listed(Chunks<double>::fwd, o->chunk64[w])))
+      return set_error(SMPC_EINVAL, "chunk64[%d] = %d is not a built chunk length", w, o->chunk64[w]);
+  }
   return SMPC_OK;
 }
 
@@ -736,11 +839,34 @@ int run_block_prec(smpc_ctx* ctx, smpc_sys* sys, Plan* p, bool fp32, int iters, 
   return fp32 ? run_block<float>(ctx, sys, p, kModeAPG, iters) : run_block<double>(ctx, sys, p, kModeAPG, iters);
 }
 
-int read_done(smpc_ctx* ctx, Plan* p) {
-  HIP_TRY(hipMemcpyAsync(p->done_host.data(), p->done.ptr, sizeof(int32_t) * p->trees.size(), hipMemcpyDeviceToHost,
-                         ctx->stream));
-  HIP_TRY(hipStreamSynchronize(ctx->stream));
-  return SMPC_OK;
+// Chunk lengths for the options' precisions: explicit entries, else -- with
+// tune and from_sys -- the system's tuned pair, else the default; with tune
+// and without from_sys a pair already marked tuned is kept.
+void choose_chunks(const smpc_sys* sys, const smpc_solve_opts* o, bool from_sys, int (&chunk)[2][2],
+                   bool (&tuned)[2]) {
+  const int* given[2] = {o->chunk64, o->chunk32};
+  const int defaults[2][2] = {{Chunks<double>::bwd[0], Chunks<double>::fwd[0]},
+                              {Chunks<float>::bwd[0], Chunks<float>::fwd[0]}};
+  for (int k = 0; k < 2; ++k) {
+    const bool explicit_pair = given[k][0] != 0 || given[k][1] != 0;
+    if (explicit_pair) {
+      for (int w = 0; w < 2; ++w) chunk[k][w] = given[k][w] ? given[k][w] : defaults[k][w];
+      tuned[k] = false;
+    } else if (o->tune && from_sys && sys->has_tuned[k]) {
+      for (int w = 0; w < 2; ++w) chunk[k][w] = sys->tuned_chunk[k][w];
+    } else if (!(o->tune && tuned[k])) {
+      for (int w = 0; w < 2; ++w) chunk[k][w] = defaults[k][w];
+      tuned[k] = false;
+    }
+  }
+}
+
+void result_chunks(const int (&chunk)[2][2], const smpc_solve_opts* o, smpc_result* r) {
+  const SolvePhases ph = phases(o);
+  for (int w = 0; w < 2; ++w) {
+    r->chunk32[w] = ph.run32 ? chunk[1][w] : 0;
+    r->chunk64[w] = ph.run64 ? chunk[0][w] : 0;
+  }
 }
 
 // Solve a set of trees (one plan) with the given options.
@@ -752,7 +878,9 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
   const int D = 2 * sys->nx + sys->nu;
   SMPC_TRY(ctx->ensure_ctab(o->max_iter + 2));
   const SolvePhases ph = phases(o);
-  const int max_rounds = o->max_iter / o->check_every + 3;
+  choose_chunks(sys, o, false, plan->chunk, plan->tuned);
+  // tuning takes at most 3 blocks per chunk pair (they are iterations too)
+  const int max_rounds = o->max_iter / o->check_every + 3 + 3 * 4;
   std::vector<int> fp32_iters(n, 0), status32(n, 0);
   size_t off = 0;
   for (int k = 0; k < n; ++k) {
@@ -763,7 +891,7 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
     off += (size_t)t->M * D;
   }
   if (ph.run32) {
-    SMPC_TRY(run_until_done<float>(ctx, sys, plan, o->check_every, max_rounds));
+    SMPC_TRY(run_until_done<float>(ctx, sys, plan, o->check_every, max_rounds, o->tune != 0));
     for (int k = 0; k < n; ++k) {
       TreeState h;
       SMPC_TRY(read_state(plan->trees[k], &h));
@@ -772,8 +900,12 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
       if (ph.run64) SMPC_TRY(tree_to_fp64(plan->trees[k], o, fp32_iters[k], status32[k]));
     }
   }
-  if (ph.run64) SMPC_TRY(run_until_done<double>(ctx, sys, plan, o->check_every, max_rounds + ph.polish + 2));
-  for (int k = 0; k < n; ++k) SMPC_TRY(tree_result(plan->trees[k], o, fp32_iters[k], status32[k], res ? &res[k] : nullptr));
+  if (ph.run64)
+    SMPC_TRY(run_until_done<double>(ctx, sys, plan, o->check_every, max_rounds + ph.polish + 2, o->tune != 0));
+  for (int k = 0; k < n; ++k) {
+    SMPC_TRY(tree_result(plan->trees[k], o, fp32_iters[k], status32[k], res ? &res[k] : nullptr));
+    if (res) result_chunks(plan->chunk, o, &res[k]);
+  }
   return SMPC_OK;
 }
 
@@ -821,6 +953,23 @@ int prepare32(smpc_tree* t) {
 // =================================================================== C ABI
 
 extern "C" {
+
+int smpc_chunk_lengths(int precision, int which, int* out, int cap, int* n) {
+  if (precision != 32 && precision != 64) return set_error(SMPC_EINVAL, "precision must be 32 or 64");
+  if (which != 0 && which != 1) return set_error(SMPC_EINVAL, "which must be 0 (backward) or 1 (forward)");
+  if (!n || cap < 0 || (cap > 0 && !out)) return set_error(SMPC_EINVAL, "bad output arguments");
+  std::vector<int> v;
+  if (precision == 32) {
+    if (which == 0) v.assign(std::begin(Chunks<float>::bwd), std::end(Chunks<float>::bwd));
+    else v.assign(std::begin(Chunks<float>::fwd), std::end(Chunks<float>::fwd));
+  } else {
+    if (which == 0) v.assign(std::begin(Chunks<double>::bwd), std::end(Chunks<double>::bwd));
+    else v.assign(std::begin(Chunks<double>::fwd), std::end(Chunks<double>::fwd));
+  }
+  for (int k = 0; k < cap && k < (int)v.size(); ++k) out[k] = v[k];
+  *n = (int)v.size();
+  return SMPC_OK;
+}
 
 int smpc_last_error(char* buf, size_t len) {
   if (buf && len) {

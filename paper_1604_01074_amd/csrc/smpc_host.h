@@ -108,6 +108,10 @@ struct smpc_sys {
   SysBuffers<float> d32;
   bool has32 = false;
   int n_trees = 0;
+  // chunk lengths {backward, forward} chosen by the last tuned solve, per
+  // precision ([0] float64, [1] float32); used by servers with tune 1
+  int tuned_chunk[2][2] = {{0, 0}, {0, 0}};
+  bool has_tuned[2] = {false, false};
 };
 
 template <typename T>
@@ -158,8 +162,13 @@ struct Plan {
   smpc::DevBuf items, td64, td32, done;
   std::vector<int32_t> done_host;
   bool has32 = false;
-  // instantiated graphs of `iters` iterations, keyed by (element size, mode, iters)
-  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+  // chunk lengths {backward, forward} in use per precision ([0] float64,
+  // [1] float32) and whether they were chosen by timing
+  int chunk[2][2] = {{0, 0}, {0, 0}};
+  bool tuned[2] = {false, false};
+  // instantiated graphs of `iters` iterations, keyed by (element size, mode,
+  // iters, backward chunk, forward chunk)
+  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
   int graphs_ctab_gen = -1;
 };
 
@@ -181,6 +190,9 @@ int tree_to_fp64(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int sta
 int tree_result(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int status32, smpc_result* r);
 int read_state(smpc_tree* t, TreeState* h);
 int run_block_prec(smpc_ctx* ctx, smpc_sys* sys, Plan* p, bool fp32, int iters, bool eager);
+void choose_chunks(const smpc_sys* sys, const smpc_solve_opts* o, bool from_sys, int (&chunk)[2][2],
+                   bool (&tuned)[2]);
+void result_chunks(const int (&chunk)[2][2], const smpc_solve_opts* o, smpc_result* r);
 int read_done(smpc_ctx* ctx, Plan* p);
 
 // smpc_setup.cpp

@@ -113,16 +113,40 @@ struct TreeDev {
   int32_t pad;
 };
 
+// Chunk lengths (nodes per chunk) the kernels are instantiated for, per
+// precision and kernel; the first entry is the default.  The chunk length
+// only changes how many nodes are staged between barriers, never the order
+// of the arithmetic, so every length gives bit-identical iterates.
+template <typename T>
+struct Chunks;
+template <>
+struct Chunks<float> {
+  static constexpr int bwd[2] = {16, 32};
+  static constexpr int fwd[2] = {8, 16};
+};
+template <>
+struct Chunks<double> {
+  static constexpr int bwd[2] = {16, 32};
+  static constexpr int fwd[2] = {8, 4};
+};
+template <int N>
+constexpr bool chunk_listed(const int (&a)[N], int v) {
+  for (int i = 0; i < N; ++i)
+    if (a[i] == v) return true;
+  return false;
+}
+
 // Kernel launchers (smpc_kernels.hip).  `items` lists the leaf chains of all
 // trees of the launch; `trees` is a device table.  One iteration is
 // launch_backward then launch_forward; `done_out[tree]` receives each tree's
-// stop flag at the end of the forward kernel.
+// stop flag at the end of the forward kernel.  `chunk` must be listed in
+// Chunks<T> (hipErrorInvalidValue otherwise).
 template <typename T>
 hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
-                           int n_items, const double* ctab, int mode, hipStream_t s);
+                           int n_items, const double* ctab, int mode, int chunk, hipStream_t s);
 template <typename T>
 hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
-                          int n_items, const double* ctab, int mode, int32_t* done_out, hipStream_t s);
+                          int n_items, const double* ctab, int mode, int chunk, int32_t* done_out, hipStream_t s);
 template <typename T>
 hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s);
 // Warm-start shift: dst0 = dst2 = f * src gathered by node (per dual block
@@ -133,7 +157,7 @@ hipError_t launch_shift(const Ts* src, Td* dst0, Td* dst2, const int32_t* src_no
 
 // Row stride of the zero-padded P on the device (and of the staged rho rows).
 __host__ __device__ int p_stride(int nu);
-__host__ __device__ size_t lds_bytes_backward(int nx, int nu, size_t elem);
-__host__ __device__ size_t lds_bytes_forward(int nx, int nu, size_t elem);
+__host__ __device__ size_t lds_bytes_backward(int nx, int nu, size_t elem, int chunk);
+__host__ __device__ size_t lds_bytes_forward(int nx, int nu, size_t elem, int chunk);
 
 }  // namespace smpc

@@ -122,18 +122,10 @@ __device__ __forceinline__ void wait_mem() {
 // what crosses components (Q for B'Q, ut for B ut, rho for the P product).
 // ---------------------------------------------------------------------------
 
-// Nodes per backward chunk: the P product of a chunk is one or two 16-row
-// MFMA tiles.
-template <typename T>
-struct ChunkLen {
-  static constexpr int value = 16;
-};
-
-// Nodes per forward chunk (register arrays of this length per thread).
-template <typename T>
-struct FwdChunk {
-  static constexpr int value = 8;
-};
+// Chunk lengths are template parameters (CH): nodes per backward chunk (the
+// P product of a chunk is CH / 16 MFMA row tiles) and nodes per forward chunk
+// (register arrays of this length per thread).  The launchers accept the
+// lengths listed in chunk_supported; the host picks one per launch plan.
 
 // 16x16x4 matrix-core products.  Operand layouts (both precisions): lane l
 // holds A[l % 16][l / 16] and B[l / 16][l % 16]; the four accumulator values
@@ -284,19 +276,19 @@ __device__ __forceinline__ T wpoint(const Iter<T>& x, int mode, uint32_t k) {
 
 __host__ __device__ int p_stride(int nu) { return nu <= 64 ? 64 : 128; }
 
-__host__ __device__ size_t lds_bytes_backward(int nx, int nu, size_t elem) {
+__host__ __device__ size_t lds_bytes_backward(int nx, int nu, size_t elem, int chunk) {
   // the two Q parts of the chunk (2 x chunk x padded nx), rho transposed (P-stride
   // rows of chunk + 1 entries), -1/(2 pi) for two chunks, two Q carries
   // (general A), the chain-top exchange
-  const size_t ch = elem == 4 ? ChunkLen<float>::value : ChunkLen<double>::value;
+  const size_t ch = (size_t)chunk;
   const size_t xs = nx <= 64 ? 64 : 128;
   return elem * (2 * ch * xs + (size_t)p_stride(nu) * (ch + 1) + 2 * ch + 3 * (size_t)nx);
 }
 
-__host__ __device__ size_t lds_bytes_forward(int nx, int nu, size_t elem) {
+__host__ __device__ size_t lds_bytes_forward(int nx, int nu, size_t elem, int chunk) {
   // ut of two chunks (2 x chunk x padded nu), scales and pi of two chunks,
   // the x carries of waves 0 and 1 (general A), 32 float64 reduction slots
-  const size_t ch = elem == 4 ? FwdChunk<float>::value : FwdChunk<double>::value;
+  const size_t ch = (size_t)chunk;
   return elem * (2 * ch * (size_t)p_stride(nu) + 8 * ch + 2 * (size_t)nx) + 32 * sizeof(double);
 }
 
@@ -314,11 +306,10 @@ namespace {
 // held in registers: wave w owns columns [16 NT w, 16 NT (w + 1)) of every
 // 4-row K step).
 // ---------------------------------------------------------------------------
-template <typename T, int KP, int NXL>
+template <typename T, int KP, int NXL, int CH>
 __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode, int chain,
                           unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
                           const RowCache<T, kNnzBt>& bt, int& par) {
-  constexpr int CH = ChunkLen<T>::value;
   constexpr int RS = CH + 1;  // row stride of the transposed rho (bank spread)
   constexpr int NT = KP / 64, KS = KP / 4, MT = CH / 16;
   constexpr int XS = 64 * NXL;  // row stride of the Q parts (>= nx, a constant)
@@ -516,13 +507,12 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
 
 // Persistent: workgroup b takes leaf chains b, b + gridDim.x, ... (longest
 // first), so the register-resident P is loaded once per workgroup.
-template <typename T, int KP, int NXL>
+template <typename T, int KP, int NXL, int CH>
 __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
                                                         const WorkItem* __restrict__ items, int n_items,
                                                         const double* __restrict__ ctab, int mode) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_last;
-  constexpr int CH = ChunkLen<T>::value;
   constexpr int NT = KP / 64, KS = KP / 4;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -554,7 +544,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
     const Iter<T> x = make_iter(td, st, ctab, mode);
     int chain = wi.chain;
     while (true) {
-      bwd_chain<T, KP, NXL>(sys, td, x, mode, chain, smem_raw, preg, bt, par);
+      bwd_chain<T, KP, NXL, CH>(sys, td, x, mode, chain, smem_raw, preg, bt, par);
       const int parent = gp(td.chains)[chain].parent;
       if (parent < 0) break;  // the root chain is done: the sweep is complete
       // this chain's top terms are stored: count this child done at the parent
@@ -620,14 +610,13 @@ __device__ __forceinline__ int32_t node_code(const G<int32_t>* __restrict__ code
 // of the psi~ blocks and the dual update.  The arrays are distinct
 // allocations (the three dual slots rotate), so the loads of later nodes may
 // be issued before the stores of earlier ones.
-template <typename T, int UP>
+template <typename T, int UP, int CH>
 __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const G<int32_t>* __restrict__ codes,
                                               int plen, int first, int k0, int C, int j, int nx, int nu, int D,
                                               const G<T>* __restrict__ du, const G<T>* __restrict__ uhat,
                                               const G<T>* __restrict__ yc, const G<T>* __restrict__ yp,
                                               const G<T>* __restrict__ scale, G<T>* __restrict__ ynew,
                                               G<T>* __restrict__ z, T* sUp, T& utc, T ulo, T uhi, Partials& pt) {
-  constexpr int CH = FwdChunk<T>::value;
   constexpr int US = UP;
   const int W = nx + nu;
   // all loads of the chunk first (unconditionally, so that they are in
@@ -682,16 +671,14 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const 
 // published: x_n = A x_above + B ut_n + e_n node by node, then the distance
 // prox of block b of owned nodes (the block norm is one wave reduction) and
 // the dual update.
-template <typename T, int NXL, int UP>
+template <typename T, int NXL, int UP, int CH>
 __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T>& x, int b,
                                                 const G<int32_t>* __restrict__ codes, int plen, int first, int k0,
                                                 int C,
-                                                const T (&ev)[NXL][FwdChunk<T>::value],
-                                                const T (&wv)[NXL][FwdChunk<T>::value],
+                                                const T (&ev)[NXL][CH], const T (&wv)[NXL][CH],
                                                 const RowCache<T, kNnzB> (&brow)[NXL], const T (&bnd)[NXL][2],
                                                 const T* sSP, G<T>* __restrict__ ynew, G<T>* __restrict__ z,
                                                 const T* sUp, T* cx, T (&xc)[NXL], Partials& pt) {
-  constexpr int CH = FwdChunk<T>::value;
   constexpr int US = UP;
   const int lane = threadIdx.x & 63;
   const int nx = sys.nx, nu = sys.nu, D = sys.D;
@@ -797,12 +784,11 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
   }
 }
 
-template <typename T, int NXL, int UP>
+template <typename T, int NXL, int UP, int CH>
 __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode,
                           const G<int32_t>* codes, int plen, int first, int len, unsigned char* smem_raw,
                           const RowCache<T, kNnzB> (&brow)[NXL], T (&xc)[NXL], T& utc, const T (&bnd)[NXL][2],
                           const T (&ubnd)[2], int& par, Partials& pt) {
-  constexpr int CH = FwdChunk<T>::value;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -825,7 +811,7 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
       sSPp[4 * tid + 3] = gp(td.pi)[n];
     }
     if (ju)
-      fwd_psi_chunk<T, UP>(mode, x, codes, plen, first, k0, C, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur,
+      fwd_psi_chunk<T, UP, CH>(mode, x, codes, plen, first, k0, C, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur,
                            x.yprv, gp(td.scale), x.ynew, gp(td.z), sUp, utc, ubnd[0], ubnd[1], pt);
     // waves 0, 1: e and the dual point of the wave's block, loaded before the
     // barrier
@@ -851,13 +837,13 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
     }
     __syncthreads();  // ut of the chunk published
     if (wave < 2)
-      fwd_state_chunk<T, NXL, UP>(sys, mode, x, b, codes, plen, first, k0, C, ev, wv, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
+      fwd_state_chunk<T, NXL, UP, CH>(sys, mode, x, b, codes, plen, first, k0, C, ev, wv, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
                                   sXc + (size_t)wave * nx, xc, pt);
     par ^= 1;
   }
 }
 
-template <typename T, int NXL, int UP>
+template <typename T, int NXL, int UP, int CH>
 __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
                                                        const WorkItem* __restrict__ items,
                                                        const double* __restrict__ ctab, int mode,
@@ -877,7 +863,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
   const Iter<T> x = make_iter(td, st, ctab, mode);
   const int nx = sys.nx, nu = sys.nu;
   const int j = tid - 128;
-  double* sRed = reinterpret_cast<double*>(smem_raw + lds_bytes_forward(nx, nu, sizeof(T)) - 32 * sizeof(double));
+  double* sRed = reinterpret_cast<double*>(smem_raw + lds_bytes_forward(nx, nu, sizeof(T), CH) - 32 * sizeof(double));
 
   // per-thread system rows, bounds and carries of the thread's role
   RowCache<T, kNnzB> brow[NXL];
@@ -903,7 +889,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const Tree
   // chain itself, as one sequence
   const int p0 = gp(td.path_off)[wi.chain], p1 = gp(td.path_off)[wi.chain + 1];
   const ChainDesc ch = gp(td.chains)[wi.chain];
-  fwd_nodes<T, NXL, UP>(sys, td, x, mode, gp(td.path) + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw, brow, xc,
+  fwd_nodes<T, NXL, UP, CH>(sys, td, x, mode, gp(td.path) + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw, brow, xc,
                         utc, bnd, ubnd, par, pt);
 
   // partials of this leaf chain
@@ -1078,54 +1064,74 @@ int resident_blocks(K kernel, size_t lds) {
   return n;
 }
 
-template <typename T, int KP, int NXL>
-hipError_t launch_backward_kp(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, int KP, int NXL, int CH>
+hipError_t launch_backward_ch(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
                               const double* ctab, int mode, hipStream_t s) {
-  const size_t lds = lds_bytes_backward(sys.nx, sys.nu, sizeof(T));
-  hipError_t e = allow_lds(k_backward<T, KP, NXL>, lds);
+  const size_t lds = lds_bytes_backward(sys.nx, sys.nu, sizeof(T), CH);
+  hipError_t e = allow_lds(k_backward<T, KP, NXL, CH>, lds);
   if (e != hipSuccess) return e;
-  const int res = resident_blocks(k_backward<T, KP, NXL>, lds);
+  const int res = resident_blocks(k_backward<T, KP, NXL, CH>, lds);
   if (res <= 0) return hipErrorInvalidValue;
   const int grid = std::min(n_items, res);
-  hipLaunchKernelGGL((k_backward<T, KP, NXL>), dim3(grid), dim3(kBlock), lds, s, sys, trees, items, n_items, ctab,
-                     mode);
+  hipLaunchKernelGGL((k_backward<T, KP, NXL, CH>), dim3(grid), dim3(kBlock), lds, s, sys, trees, items, n_items,
+                     ctab, mode);
   return hipGetLastError();
+}
+
+template <typename T, int KP, int NXL>
+hipError_t launch_backward_kp(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+                              const double* ctab, int mode, int chunk, hipStream_t s) {
+  if (chunk == 16) return launch_backward_ch<T, KP, NXL, 16>(sys, trees, items, n_items, ctab, mode, s);
+  if constexpr (chunk_listed(Chunks<T>::bwd, 32))
+    if (chunk == 32) return launch_backward_ch<T, KP, NXL, 32>(sys, trees, items, n_items, ctab, mode, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
-                           const double* ctab, int mode, hipStream_t s) {
+                           const double* ctab, int mode, int chunk, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (sys.nx > 128 || sys.nu > 128) return hipErrorInvalidValue;
+  if (sys.nx > 128 || sys.nu > 128 || !chunk_listed(Chunks<T>::bwd, chunk)) return hipErrorInvalidValue;
   const bool x1 = sys.nx <= 64;
   if (sys.nu <= 64)
-    return x1 ? launch_backward_kp<T, 64, 1>(sys, trees, items, n_items, ctab, mode, s)
-              : launch_backward_kp<T, 64, 2>(sys, trees, items, n_items, ctab, mode, s);
-  return x1 ? launch_backward_kp<T, 128, 1>(sys, trees, items, n_items, ctab, mode, s)
-            : launch_backward_kp<T, 128, 2>(sys, trees, items, n_items, ctab, mode, s);
+    return x1 ? launch_backward_kp<T, 64, 1>(sys, trees, items, n_items, ctab, mode, chunk, s)
+              : launch_backward_kp<T, 64, 2>(sys, trees, items, n_items, ctab, mode, chunk, s);
+  return x1 ? launch_backward_kp<T, 128, 1>(sys, trees, items, n_items, ctab, mode, chunk, s)
+            : launch_backward_kp<T, 128, 2>(sys, trees, items, n_items, ctab, mode, chunk, s);
+}
+
+template <typename T, int NXL, int UP, int CH>
+hipError_t launch_forward_ch(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+                             const double* ctab, int mode, int32_t* done_out, hipStream_t s) {
+  const size_t lds = lds_bytes_forward(sys.nx, sys.nu, sizeof(T), CH);
+  hipError_t e = allow_lds(k_forward<T, NXL, UP, CH>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_forward<T, NXL, UP, CH>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab,
+                     mode, done_out);
+  return hipGetLastError();
 }
 
 template <typename T, int NXL, int UP>
 hipError_t launch_forward_t(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
-                            const double* ctab, int mode, int32_t* done_out, hipStream_t s) {
-  const size_t lds = lds_bytes_forward(sys.nx, sys.nu, sizeof(T));
-  hipError_t e = allow_lds(k_forward<T, NXL, UP>, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_forward<T, NXL, UP>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab, mode,
-                     done_out);
-  return hipGetLastError();
+                            const double* ctab, int mode, int chunk, int32_t* done_out, hipStream_t s) {
+  if (chunk == 8) return launch_forward_ch<T, NXL, UP, 8>(sys, trees, items, n_items, ctab, mode, done_out, s);
+  if constexpr (chunk_listed(Chunks<T>::fwd, 16))
+    if (chunk == 16) return launch_forward_ch<T, NXL, UP, 16>(sys, trees, items, n_items, ctab, mode, done_out, s);
+  if constexpr (chunk_listed(Chunks<T>::fwd, 4))
+    if (chunk == 4) return launch_forward_ch<T, NXL, UP, 4>(sys, trees, items, n_items, ctab, mode, done_out, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
-                          const double* ctab, int mode, int32_t* done_out, hipStream_t s) {
+                          const double* ctab, int mode, int chunk, int32_t* done_out, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (sys.nu > 128 || sys.nx > 128) return hipErrorInvalidValue;
+  if (sys.nu > 128 || sys.nx > 128 || !chunk_listed(Chunks<T>::fwd, chunk)) return hipErrorInvalidValue;
   const bool x1 = sys.nx <= 64, u1 = sys.nu <= 64;
-  if (x1) return u1 ? launch_forward_t<T, 1, 64>(sys, trees, items, n_items, ctab, mode, done_out, s)
-                    : launch_forward_t<T, 1, 128>(sys, trees, items, n_items, ctab, mode, done_out, s);
-  return u1 ? launch_forward_t<T, 2, 64>(sys, trees, items, n_items, ctab, mode, done_out, s)
-            : launch_forward_t<T, 2, 128>(sys, trees, items, n_items, ctab, mode, done_out, s);
+  if (x1) return u1 ? launch_forward_t<T, 1, 64>(sys, trees, items, n_items, ctab, mode, chunk, done_out, s)
+                    : launch_forward_t<T, 1, 128>(sys, trees, items, n_items, ctab, mode, chunk, done_out, s);
+  return u1 ? launch_forward_t<T, 2, 64>(sys, trees, items, n_items, ctab, mode, chunk, done_out, s)
+            : launch_forward_t<T, 2, 128>(sys, trees, items, n_items, ctab, mode, chunk, done_out, s);
 }
 
 template <typename T>
@@ -1137,13 +1143,13 @@ hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s) {
 }
 
 template hipError_t launch_backward<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
-                                            const double*, int, hipStream_t);
+                                            const double*, int, int, hipStream_t);
 template hipError_t launch_backward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
-                                           const double*, int, hipStream_t);
+                                           const double*, int, int, hipStream_t);
 template hipError_t launch_forward<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
-                                           const double*, int, int32_t*, hipStream_t);
+                                           const double*, int, int, int32_t*, hipStream_t);
 template hipError_t launch_forward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
-                                          const double*, int, int32_t*, hipStream_t);
+                                          const double*, int, int, int32_t*, hipStream_t);
 template hipError_t launch_widen<float>(const float*, double*, size_t, hipStream_t);
 
 template <typename Ts, typename Td>

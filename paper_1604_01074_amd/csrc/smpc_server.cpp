@@ -55,6 +55,7 @@ struct smpc_server {
   smpc_sys* sys = nullptr;
   smpc_solve_opts o{};
   int max_active = 0;
+  int chunk[2][2] = {{0, 0}, {0, 0}};  // chunk lengths of its launch groups ([0] float64, [1] float32)
   std::thread worker;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -111,7 +112,10 @@ int sync_group(smpc_server* S, int g) {
   S->group[g] = nullptr;
   S->members[g] = want;
   if (want.empty()) return SMPC_OK;
-  return plan_build(ctx, want, g == 0, &S->group[g]);
+  SMPC_TRY(plan_build(ctx, want, g == 0, &S->group[g]));
+  for (int k = 0; k < 2; ++k)
+    for (int w = 0; w < 2; ++w) S->group[g]->chunk[k][w] = S->chunk[k][w];
+  return SMPC_OK;
 }
 
 void worker_main(smpc_server* S) {
@@ -204,6 +208,7 @@ void worker_main(smpc_server* S) {
         r->res.u0 = r->u0.data();
         code = tree_result(r->t, &S->o, r->fp32_iters, r->status32, &r->res);
         r->res.u0 = nullptr;
+        result_chunks(S->chunk, &S->o, &r->res);
       }
       if (code >= 0) code = r->res.status;
       finish(S, r, code, code < 0 ? last_error_text() : nullptr);
@@ -233,6 +238,8 @@ int smpc_server_create(smpc_sys* sys, const smpc_server_opts* opts, smpc_server*
   S->o = opts->solve;
   S->o.y0 = S->o.y_prev0 = nullptr;
   S->max_active = opts->max_active;
+  bool tuned[2] = {false, false};
+  choose_chunks(sys, &S->o, true, S->chunk, tuned);
   try {
     S->worker = std::thread(worker_main, S);
   } catch (...) {

@@ -33,6 +33,7 @@ EXPORTED = [
     "smpc_solve", "smpc_solve_batch", "smpc_shift_warm_start", "smpc_solve_step",
     "smpc_ctx_set_profiling", "smpc_ctx_kernel_stats", "smpc_ctx_reset_stats",
     "smpc_server_create", "smpc_server_submit", "smpc_server_poll", "smpc_server_destroy",
+    "smpc_chunk_lengths",
 ]
 
 
@@ -80,13 +81,15 @@ class FactorOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("precision", C.c_int), ("polish_iters", C.c_int), ("warm_start", C.c_int),
-                ("y0", _dp), ("y_prev0", _dp), ("stall_checks", C.c_int)]
+                ("y0", _dp), ("y_prev0", _dp), ("stall_checks", C.c_int), ("tune", C.c_int),
+                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2)]
 
 
 class Result(C.Structure):
     _fields_ = [("u0", _dp), ("x", _dp), ("u", _dp), ("y", _dp), ("iterations", C.c_int),
                 ("fp32_iterations", C.c_int), ("r_primal", C.c_double), ("hz_t_max", C.c_double),
-                ("status", C.c_int), ("queue_ms", C.c_double), ("run_ms", C.c_double)]
+                ("status", C.c_int), ("queue_ms", C.c_double), ("run_ms", C.c_double),
+                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2)]
 
 
 class ServerOpts(C.Structure):
@@ -122,6 +125,7 @@ _sig = {
     "smpc_server_submit": [_vp, _vp, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.POINTER(C.c_uint64)],
     "smpc_server_poll": [_vp, C.c_uint64, C.POINTER(Result), C.c_int],
     "smpc_server_destroy": [_vp],
+    "smpc_chunk_lengths": [C.c_int, C.c_int, _ip, C.c_int, _ip],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -244,13 +248,22 @@ def smpc_tree_get_factor(t, with_scale: bool = False):
 
 # ---------------------------------------------------------------- solve
 
-def _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks=0, resident=False):
+def _pair(v):
+    a = (C.c_int * 2)()
+    if v is not None:
+        a[0], a[1] = int(v[0]), int(v[1])
+    return a
+
+
+def _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks=0, resident=False,
+          tune=0, chunk32=None, chunk64=None):
     keep = [None if y0 is None else _f64(y0), None if y_prev0 is None else _f64(y_prev0)]
     if resident and y0 is not None:
         raise ValueError("a resident warm start and y0 exclude each other")
     warm = 1 if resident else (2 if y0 is not None else 0)
     o = SolveOpts(float(tol), int(max_iter), int(check_every), int(precision), int(polish_iters),
-                  warm, _ptr(keep[0]), _ptr(keep[1]), int(stall_checks))
+                  warm, _ptr(keep[0]), _ptr(keep[1]), int(stall_checks), int(tune), _pair(chunk32),
+                  _pair(chunk64))
     return o, keep
 
 
@@ -262,23 +275,24 @@ def _result(M, nx, nu, want_x, want_y):
         out["u"] = np.empty((M, nu))
     if want_y:
         out["y"] = np.empty((M, D))
-    r = Result(_ptr(out["u0"]), _ptr(out.get("x")), _ptr(out.get("u")), _ptr(out.get("y")), 0, 0, 0.0, 0.0, 0,
-               0.0, 0.0)
+    r = Result(_ptr(out["u0"]), _ptr(out.get("x")), _ptr(out.get("u")), _ptr(out.get("y")))
     return r, out
 
 
 def _finish(r: Result, out: dict) -> dict:
     out.update(iterations=r.iterations, fp32_iterations=r.fp32_iterations, r_primal=r.r_primal,
-               hz_t_max=r.hz_t_max, status=r.status)
+               hz_t_max=r.hz_t_max, status=r.status, chunk32=tuple(r.chunk32), chunk64=tuple(r.chunk64))
     return out
 
 
 def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precision=64, polish_iters=0,
-               y0=None, y_prev0=None, want_x=True, want_y=True, stall_checks=0, resident=False) -> dict:
+               y0=None, y_prev0=None, want_x=True, want_y=True, stall_checks=0, resident=False, tune=0,
+               chunk32=None, chunk64=None) -> dict:
     """``dims = (M, nx, nu)``.  Returns a dict with u0, x, u, y, iterations,
-    fp32_iterations, r_primal, hz_t_max, status."""
+    fp32_iterations, r_primal, hz_t_max, status, chunk32, chunk64."""
     M, nx, nu = dims
-    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident)
+    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident,
+                    tune, chunk32, chunk64)
     r, out = _result(M, nx, nu, want_x, want_y)
     pp, qq = _f64(p), _f64(q)
     _check_solve(_lib.smpc_solve(t, _ptr(pp), _ptr(qq), C.byref(o), C.byref(r)))
@@ -287,9 +301,10 @@ def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precis
 
 def smpc_solve_batch(trees, ps, qs, *, dims_list, tol=1e-3, max_iter=1000, check_every=10, precision=64,
                      polish_iters=0, y0=None, y_prev0=None, want_x=True, want_y=True,
-                     stall_checks=0, resident=False) -> tuple[int, list]:
+                     stall_checks=0, resident=False, tune=0, chunk32=None, chunk64=None) -> tuple[int, list]:
     n = len(trees)
-    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident)
+    o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident,
+                    tune, chunk32, chunk64)
     res = (Result * n)()
     outs = []
     for k, (M, nx, nu) in enumerate(dims_list):
@@ -318,6 +333,16 @@ def smpc_solve_step(t, p, q, w, *, dims, precision=64):
     return x, u
 
 
+def smpc_chunk_lengths(precision: int, which: int) -> list:
+    """Chunk lengths built for ``precision`` (32, 64) and kernel ``which``
+    (0 backward, 1 forward), default first."""
+    n = C.c_int32()
+    _check(_lib.smpc_chunk_lengths(int(precision), int(which), None, 0, C.byref(n)))
+    arr = (C.c_int32 * max(n.value, 1))()
+    _check(_lib.smpc_chunk_lengths(int(precision), int(which), arr, n.value, C.byref(n)))
+    return [arr[k] for k in range(n.value)]
+
+
 # ---------------------------------------------------------------- profiling
 
 def smpc_ctx_set_profiling(ctx, enable: bool) -> None:
@@ -339,8 +364,9 @@ def smpc_ctx_reset_stats(ctx) -> None:
 # ---------------------------------------------------------------- serving
 
 def smpc_server_create(sys_handle, *, tol=1e-3, max_iter=1000, check_every=10, precision=32, polish_iters=20,
-                       stall_checks=0, max_active=0):
-    o, _ = _opts(tol, max_iter, check_every, precision, polish_iters, None, None, stall_checks)
+                       stall_checks=0, max_active=0, tune=0, chunk32=None, chunk64=None):
+    o, _ = _opts(tol, max_iter, check_every, precision, polish_iters, None, None, stall_checks, False, tune,
+                 chunk32, chunk64)
     so = ServerOpts(o, int(max_active))
     h = _vp()
     _check(_lib.smpc_server_create(sys_handle, C.byref(so), C.byref(h)))
@@ -361,14 +387,15 @@ def smpc_server_poll(srv, ticket: int, nu: int, wait_ms: int = -1):
     """None while the request runs, else a dict with u0, iterations,
     fp32_iterations, r_primal, hz_t_max, status, queue_ms, run_ms."""
     u0 = np.empty(nu)
-    r = Result(_ptr(u0), None, None, None, 0, 0, 0.0, 0.0, 0, 0.0, 0.0)
+    r = Result(_ptr(u0), None, None, None)
     code = _lib.smpc_server_poll(srv, C.c_uint64(ticket), C.byref(r), int(wait_ms))
     if code == PENDING:
         return None
     if code < 0 and code != EDIVERGED:
         raise SmpcError(code, last_error())
     return dict(u0=u0, iterations=r.iterations, fp32_iterations=r.fp32_iterations, r_primal=r.r_primal,
-                hz_t_max=r.hz_t_max, status=r.status, queue_ms=r.queue_ms, run_ms=r.run_ms)
+                hz_t_max=r.hz_t_max, status=r.status, queue_ms=r.queue_ms, run_ms=r.run_ms,
+                chunk32=tuple(r.chunk32), chunk64=tuple(r.chunk64))
 
 
 def smpc_server_destroy(srv) -> None:

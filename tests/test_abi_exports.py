@@ -39,3 +39,22 @@ def test_binding_covers_every_declared_symbol():
     assert sorted(smpc.EXPORTED) == _declared()
     for n in smpc.EXPORTED:
         assert callable(getattr(smpc, n, None)) or n == "smpc_last_error"
+
+
+def test_chunk_length_query_runs_without_a_gpu():
+    from paper_1604_01074_amd import smpc
+
+    for precision in (32, 64):
+        for which in (0, 1):
+            lens = smpc.smpc_chunk_lengths(precision, which)
+            assert len(lens) >= 1 and len(set(lens)) == len(lens)
+            assert all(n in (4, 8, 16, 32) for n in lens)
+    # the defaults come first
+    assert smpc.smpc_chunk_lengths(32, 0)[0] == 16 and smpc.smpc_chunk_lengths(64, 1)[0] == 8
+    for bad in ((16, 0), (32, 2)):
+        try:
+            smpc.smpc_chunk_lengths(*bad)
+        except smpc.SmpcError as e:
+            assert e.code == smpc.EINVAL
+        else:
+            raise AssertionError(bad)
