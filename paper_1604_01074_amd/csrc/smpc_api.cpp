@@ -248,6 +248,9 @@ int ensure_sys32(smpc_sys* s) {
 
 // Allocate the per-precision node buffers of a tree and upload what is known.
 template <typename T>
+int tree_upload_scale(smpc_tree* t);
+
+template <typename T>
 int tree_alloc(smpc_tree* t) {
   TreeBuffers<T>& b = treebuf<T>(t);
   smpc_ctx* ctx = t->sys->ctx;
@@ -269,6 +272,7 @@ int tree_alloc(smpc_tree* t) {
     std::vector<double> pii(M);
     for (size_t i = 0; i < M; ++i) pii[i] = t->prob[t->perm[i]];
     SMPC_TRY(upload<T>(ctx, b.pi, pii.data(), M));
+    SMPC_TRY(tree_upload_scale<T>(t));
   }
   TreeDev<T>& v = b.view;
   for (int k = 0; k < 3; ++k) v.y[k] = (T*)b.y[k].ptr;
@@ -276,7 +280,7 @@ int tree_alloc(smpc_tree* t) {
   v.uhat = (const T*)b.uhat.ptr;
   v.e = (const T*)b.e.ptr;
   v.pi = (const T*)b.pi.ptr;
-  v.scale = t->scale.empty() ? nullptr : (const T*)b.scale.ptr;
+  v.scale = (const T*)b.scale.ptr;  // ones when the tree is unscaled
   v.p = (const T*)b.p.ptr;
   v.du = (T*)b.du.ptr;
   v.z = (T*)b.z.ptr;
@@ -314,10 +318,15 @@ int tree_upload_data(smpc_tree* t) {
   return SMPC_OK;
 }
 
+// The device scaling is always present: an unscaled tree holds ones, so the
+// kernels multiply by it unconditionally (exactly).
 template <typename T>
 int tree_upload_scale(smpc_tree* t) {
   TreeBuffers<T>& b = treebuf<T>(t);
-  if (t->scale.empty()) return SMPC_OK;
+  if (t->scale.empty()) {
+    const std::vector<double> ones((size_t)t->M * 3, 1.0);
+    return upload<T>(t->sys->ctx, b.scale, ones.data(), ones.size());
+  }
   return upload<T>(t->sys->ctx, b.scale, t->scale.data(), t->scale.size());
 }
 

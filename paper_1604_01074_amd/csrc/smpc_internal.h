@@ -31,6 +31,7 @@ enum Mode : int {
   kModeAPG = 0,     // one APG iteration (extrapolate, solve step, prox, update)
   kModeSolve = 1,   // solve step only at w = y[0]; writes z
   kModePower = 2,   // linear part of the dual gradient, for the power iteration
+  kModeAny = -1,    // kernel template argument: the mode is a run-time argument
 };
 
 struct ChainDesc {
@@ -127,7 +128,7 @@ struct Chunks<float> {
 template <>
 struct Chunks<double> {
   static constexpr int bwd[2] = {16, 32};
-  static constexpr int fwd[2] = {8, 4};
+  static constexpr int fwd[2] = {4, 8};
 };
 template <int N>
 constexpr bool chunk_listed(const int (&a)[N], int v) {

@@ -253,7 +253,7 @@ __device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const G<TreeS
   }
   if (mode == kModePower) x.in_scale = (T)st->in_scale;
   x.affine = mode != kModePower;
-  x.scaled = (td.scale != nullptr) && (mode != kModeSolve);
+  x.scaled = mode != kModeSolve;  // an unscaled tree holds ones
   const bool check = (mode != kModeAPG) || ((x.it + 1) % st->check_every == 0) || (x.it + 1 >= st->max_iter);
   x.write_z = (mode == kModeSolve) || (mode == kModeAPG && check);
   x.ycur = gp(td.y[x.it % 3]);
@@ -378,20 +378,33 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
 #pragma unroll
       for (int r = 0; r < NXL; ++r) {
         const int i = lane + 64 * r;
+        const uint32_t ic = (uint32_t)(i < nx ? i : 0);
 #pragma unroll
-        for (int cc = CH - 1; cc >= 0; --cc) {
-          if (cc < C && i < nx) {
-            const uint32_t n = (uint32_t)(nb + cc);
+        for (int g = CH - kLoadBatch; g >= 0; g -= kLoadBatch) {
+          if (g >= C) continue;  // wave-uniform: the batch lies past the chunk's end
+          // every load of the batch first, unconditionally (nodes past the
+          // chunk's end read its last node, lanes past nx component 0), so
+          // that they are in flight together; then the recursion
+          T xi[kLoadBatch];
+#pragma unroll
+          for (int k = kLoadBatch - 1; k >= 0; --k) {
+            const uint32_t n = (uint32_t)(nb + (g + k < C ? g + k : C - 1));
             const T sb = x.scaled ? gp(td.scale)[n * 3 + b] : T(1);
-            const T xi = sb * wpoint(x, mode, n * D + b * nx + i);
-            if (sys.a_identity) {
-              qc[r] += xi;
-              sQw[cc * XS + i] = qc[r];
-            } else {
-              sQw[cc * XS + i] = xi;
+            xi[k] = sb * wpoint(x, mode, n * D + b * nx + ic);
+          }
+#pragma unroll
+          for (int k = kLoadBatch - 1; k >= 0; --k) {
+            const int cc = g + k;
+            if (cc < C && i < nx) {
+              if (sys.a_identity) {
+                qc[r] += xi[k];
+                sQw[cc * XS + i] = qc[r];
+              } else {
+                sQw[cc * XS + i] = xi[k];
+              }
             }
           }
-          if (cc % kLoadBatch == 0) __builtin_amdgcn_sched_barrier(0);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       if (!sys.a_identity) {
@@ -427,14 +440,23 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
       }
     }
     if (ju) {
-      // r_n = beta_n + S w_psi, parked in this thread's row of the rho tile
+      // r_n = beta_n + S w_psi, parked in this thread's row of the rho tile;
+      // loads batched as above
 #pragma unroll
-      for (int cc = 0; cc < CH; ++cc)
-        if (cc < C) {
-          const uint32_t n = (uint32_t)(nb + cc);
+      for (int g = 0; g < CH; g += kLoadBatch) {
+        if (g >= C) break;  // wave-uniform
+        T rv[kLoadBatch];
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k) {
+          const uint32_t n = (uint32_t)(nb + (g + k < C ? g + k : C - 1));
           const T s2 = x.scaled ? gp(td.scale)[n * 3 + 2] : T(1);
-          sRt[j * RS + cc] = (x.affine ? gp(td.beta)[n * nu + j] : T(0)) + s2 * wpoint(x, mode, n * D + 2 * nx + j);
+          rv[k] = (x.affine ? gp(td.beta)[n * nu + j] : T(0)) + s2 * wpoint(x, mode, n * D + 2 * nx + j);
         }
+#pragma unroll
+        for (int k = 0; k < kLoadBatch; ++k)
+          if (g + k < C) sRt[j * RS + g + k] = rv[k];
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
     __syncthreads();  // Q parts complete
     if (ju) {
@@ -507,10 +529,11 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
 
 // Persistent: workgroup b takes leaf chains b, b + gridDim.x, ... (longest
 // first), so the register-resident P is loaded once per workgroup.
-template <typename T, int KP, int NXL, int CH>
+template <typename T, int KP, int NXL, int CH, int MODE>
 __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
                                                         const WorkItem* __restrict__ items, int n_items,
-                                                        const double* __restrict__ ctab, int mode) {
+                                                        const double* __restrict__ ctab, int mode_arg) {
+  const int mode = MODE == kModeAny ? mode_arg : MODE;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_last;
   constexpr int NT = KP / 64, KS = KP / 4;
@@ -606,41 +629,40 @@ __device__ __forceinline__ int32_t node_code(const G<int32_t>* __restrict__ code
   return k < plen ? codes[k] : -1 - (first + k - plen);
 }
 
+// Node code of chunk entry cc from the wave's code register (lane cc holds
+// entry cc of the chunk; entries past the sequence repeat its last node).
+__device__ __forceinline__ int32_t chunk_code(int32_t cl, int cc) { return __builtin_amdgcn_readlane(cl, cc); }
+
 // Waves 2-3, one chunk: ut_n = ut_above + du_n, u = ut + uhat, the input box
 // of the psi~ blocks and the dual update.  The arrays are distinct
 // allocations (the three dual slots rotate), so the loads of later nodes may
 // be issued before the stores of earlier ones.
 template <typename T, int UP, int CH>
-__device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const G<int32_t>* __restrict__ codes,
-                                              int plen, int first, int k0, int C, int j, int nx, int nu, int D,
+__device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_t cl, int C, int j, int nx, int nu,
+                                              int D,
                                               const G<T>* __restrict__ du, const G<T>* __restrict__ uhat,
                                               const G<T>* __restrict__ yc, const G<T>* __restrict__ yp,
                                               const G<T>* __restrict__ scale, G<T>* __restrict__ ynew,
                                               G<T>* __restrict__ z, T* sUp, T& utc, T ulo, T uhi, Partials& pt) {
   constexpr int US = UP;
   const int W = nx + nu;
-  // all loads of the chunk first (unconditionally, so that they are in
-  // flight together), then the recursion, the prox and the stores
+  // all loads of the chunk first, unconditionally (entries past the chunk's
+  // end read a valid node), so that they are in flight together; then the
+  // recursion, the prox and the stores
   T duv[CH], uhv[CH], wv[CH], sv[CH];
 #pragma unroll
   for (int cc = 0; cc < CH; ++cc) {
-    duv[cc] = uhv[cc] = wv[cc] = T(0);
-    sv[cc] = T(1);
-    if (cc < C) {
-      const int32_t code = node_code(codes, plen, first, k0 + cc);
-      const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
-      duv[cc] = du[n * nu + j];
-      if (x.affine) uhv[cc] = uhat[n * nu + j];
-      if (mode != kModeSolve) {
-        wv[cc] = wpoint2(mode, x.c, x.in_scale, yc, yp, n * D + 2 * nx + j);
-        if (x.scaled) sv[cc] = scale[n * 3 + 2];
-      }
-    }
+    const int32_t code = chunk_code(cl, cc);
+    const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
+    duv[cc] = du[n * nu + j];
+    uhv[cc] = x.affine ? uhat[n * nu + j] : T(0);
+    wv[cc] = mode != kModeSolve ? wpoint2(mode, x.c, x.in_scale, yc, yp, n * D + 2 * nx + j) : T(0);
+    sv[cc] = x.scaled ? scale[n * 3 + 2] : T(1);
   }
 #pragma unroll
   for (int cc = 0; cc < CH; ++cc)
     if (cc < C) {
-      const int32_t code = node_code(codes, plen, first, k0 + cc);
+      const int32_t code = chunk_code(cl, cc);
       const bool own = code < 0;
       const uint32_t n = (uint32_t)(own ? -1 - code : code);
       utc += duv[cc];
@@ -672,8 +694,7 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, const 
 // prox of block b of owned nodes (the block norm is one wave reduction) and
 // the dual update.
 template <typename T, int NXL, int UP, int CH>
-__device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T>& x, int b,
-                                                const G<int32_t>* __restrict__ codes, int plen, int first, int k0,
+__device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T>& x, int b, int32_t cl,
                                                 int C,
                                                 const T (&ev)[NXL][CH], const T (&wv)[NXL][CH],
                                                 const RowCache<T, kNnzB> (&brow)[NXL], const T (&bnd)[NXL][2],
@@ -734,7 +755,7 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
         }
       }
     }
-    const int32_t code = node_code(codes, plen, first, k0 + cc);
+    const int32_t code = chunk_code(cl, cc);
     if (code >= 0) continue;  // wave-uniform: the node is owned elsewhere
     const uint32_t n = (uint32_t)(-1 - code);
     if (x.write_z && b == 0) {
@@ -799,55 +820,68 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
   T* sSP = sU + 2 * CH * UP;               // 2 x CH x 4: scales and pi of the chunk's nodes
   T* sXc = sSP + 2 * 4 * CH;               // 2 x nx (general A: carries of waves 0, 1)
 
+  // every wave keeps the node codes of the current chunk in a register
+  // (lane k: entry k0 + k; entries past the sequence repeat its last node),
+  // and loads the next chunk's while the current one runs
+  const int last = len - 1;
+  int32_t cl = node_code(codes, plen, first, lane < last ? lane : last);
   for (int k0 = 0; k0 < len; k0 += CH) {
     const int C = len - k0 < CH ? len - k0 : CH;
+    const int32_t cur = cl;
+    if (k0 + CH < len) cl = node_code(codes, plen, first, k0 + CH + lane < last ? k0 + CH + lane : last);
     T* sUp = sU + par * CH * UP;
     T* sSPp = sSP + par * 4 * CH;
     if (tid < C) {
-      const int32_t code = node_code(codes, plen, first, k0 + tid);
+      const int32_t code = cur;  // wave 0: lane tid holds entry k0 + tid
       const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
       sSPp[4 * tid] = x.scaled ? gp(td.scale)[n * 3] : T(1);
       sSPp[4 * tid + 1] = x.scaled ? gp(td.scale)[n * 3 + 1] : T(1);
       sSPp[4 * tid + 3] = gp(td.pi)[n];
     }
     if (ju)
-      fwd_psi_chunk<T, UP, CH>(mode, x, codes, plen, first, k0, C, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur,
-                           x.yprv, gp(td.scale), x.ynew, gp(td.z), sUp, utc, ubnd[0], ubnd[1], pt);
+      fwd_psi_chunk<T, UP, CH>(mode, x, cur, C, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur, x.yprv,
+                               gp(td.scale), x.ynew, gp(td.z), sUp, utc, ubnd[0], ubnd[1], pt);
     // waves 0, 1: e and the dual point of the wave's block, loaded before the
-    // barrier
+    // barrier, unconditionally (a node owned elsewhere loads a value it does
+    // not use; lanes past nx read component 0)
     const int b = wave;  // 0: sigma~, 1: zeta~
     T wv[NXL][CH], ev[NXL][CH];
     if (wave < 2) {
 #pragma unroll
       for (int r = 0; r < NXL; ++r) {
         const int i = lane + 64 * r;
+        const uint32_t ic = (uint32_t)(i < nx ? i : 0);
 #pragma unroll
         for (int cc = 0; cc < CH; ++cc) {
-          wv[r][cc] = T(0);
-          ev[r][cc] = T(0);
-          if (cc < C && i < nx) {
-            const int32_t code = node_code(codes, plen, first, k0 + cc);
-            const bool own = code < 0;
-            const uint32_t n = (uint32_t)(own ? -1 - code : code);
-            if (x.affine) ev[r][cc] = gp(td.e)[n * nx + i];
-            if (own && mode != kModeSolve) wv[r][cc] = wpoint(x, mode, n * D + b * nx + i);
-          }
+          const int32_t code = chunk_code(cur, cc);
+          const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
+          ev[r][cc] = x.affine ? gp(td.e)[n * nx + ic] : T(0);
+          wv[r][cc] = mode != kModeSolve ? wpoint(x, mode, n * D + b * nx + ic) : T(0);
         }
+        if (NXL > 1) __builtin_amdgcn_sched_barrier(0);  // one state row's loads in flight at a time
       }
     }
     __syncthreads();  // ut of the chunk published
     if (wave < 2)
-      fwd_state_chunk<T, NXL, UP, CH>(sys, mode, x, b, codes, plen, first, k0, C, ev, wv, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
-                                  sXc + (size_t)wave * nx, xc, pt);
+      fwd_state_chunk<T, NXL, UP, CH>(sys, mode, x, b, cur, C, ev, wv, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
+                                      sXc + (size_t)wave * nx, xc, pt);
     par ^= 1;
   }
 }
 
-template <typename T, int NXL, int UP, int CH>
-__global__ __launch_bounds__(kBlock, 2) void k_forward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
+// Two workgroups per CU, except float64 with two state rows per lane and
+// 8-node chunks: that one needs more than 256 registers per lane.
+template <typename T, int NXL, int CH>
+constexpr int fwd_min_blocks() {
+  return (sizeof(T) == 8 && NXL > 1 && CH > 4) ? 1 : 2;
+}
+
+template <typename T, int NXL, int UP, int CH, int MODE>
+__global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
                                                        const WorkItem* __restrict__ items,
-                                                       const double* __restrict__ ctab, int mode,
+                                                       const double* __restrict__ ctab, int mode_arg,
                                                        int32_t* __restrict__ done_out) {
+  const int mode = MODE == kModeAny ? mode_arg : MODE;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_last;
   const int tid = threadIdx.x;
@@ -1064,26 +1098,32 @@ int resident_blocks(K kernel, size_t lds) {
   return n;
 }
 
-template <typename T, int KP, int NXL, int CH>
+// The APG iteration has an instantiation per chunk length with the mode
+// fixed; the power iteration and the solve step share one with the mode a
+// run-time argument and the default chunk length (the chunk length never
+// changes the result).
+template <typename T, int KP, int NXL, int CH, int MODE>
 hipError_t launch_backward_ch(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
                               const double* ctab, int mode, hipStream_t s) {
   const size_t lds = lds_bytes_backward(sys.nx, sys.nu, sizeof(T), CH);
-  hipError_t e = allow_lds(k_backward<T, KP, NXL, CH>, lds);
+  hipError_t e = allow_lds(k_backward<T, KP, NXL, CH, MODE>, lds);
   if (e != hipSuccess) return e;
-  const int res = resident_blocks(k_backward<T, KP, NXL, CH>, lds);
+  const int res = resident_blocks(k_backward<T, KP, NXL, CH, MODE>, lds);
   if (res <= 0) return hipErrorInvalidValue;
   const int grid = std::min(n_items, res);
-  hipLaunchKernelGGL((k_backward<T, KP, NXL, CH>), dim3(grid), dim3(kBlock), lds, s, sys, trees, items, n_items,
-                     ctab, mode);
+  hipLaunchKernelGGL((k_backward<T, KP, NXL, CH, MODE>), dim3(grid), dim3(kBlock), lds, s, sys, trees, items,
+                     n_items, ctab, mode);
   return hipGetLastError();
 }
 
 template <typename T, int KP, int NXL>
 hipError_t launch_backward_kp(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
                               const double* ctab, int mode, int chunk, hipStream_t s) {
-  if (chunk == 16) return launch_backward_ch<T, KP, NXL, 16>(sys, trees, items, n_items, ctab, mode, s);
+  if (mode != kModeAPG)
+    return launch_backward_ch<T, KP, NXL, Chunks<T>::bwd[0], kModeAny>(sys, trees, items, n_items, ctab, mode, s);
+  if (chunk == 16) return launch_backward_ch<T, KP, NXL, 16, kModeAPG>(sys, trees, items, n_items, ctab, mode, s);
   if constexpr (chunk_listed(Chunks<T>::bwd, 32))
-    if (chunk == 32) return launch_backward_ch<T, KP, NXL, 32>(sys, trees, items, n_items, ctab, mode, s);
+    if (chunk == 32) return launch_backward_ch<T, KP, NXL, 32, kModeAPG>(sys, trees, items, n_items, ctab, mode, s);
   return hipErrorInvalidValue;
 }
 
@@ -1100,25 +1140,31 @@ hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const 
             : launch_backward_kp<T, 128, 2>(sys, trees, items, n_items, ctab, mode, chunk, s);
 }
 
-template <typename T, int NXL, int UP, int CH>
+template <typename T, int NXL, int UP, int CH, int MODE>
 hipError_t launch_forward_ch(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
                              const double* ctab, int mode, int32_t* done_out, hipStream_t s) {
   const size_t lds = lds_bytes_forward(sys.nx, sys.nu, sizeof(T), CH);
-  hipError_t e = allow_lds(k_forward<T, NXL, UP, CH>, lds);
+  hipError_t e = allow_lds(k_forward<T, NXL, UP, CH, MODE>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_forward<T, NXL, UP, CH>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab,
-                     mode, done_out);
+  hipLaunchKernelGGL((k_forward<T, NXL, UP, CH, MODE>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items,
+                     ctab, mode, done_out);
   return hipGetLastError();
 }
 
 template <typename T, int NXL, int UP>
 hipError_t launch_forward_t(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
                             const double* ctab, int mode, int chunk, int32_t* done_out, hipStream_t s) {
-  if (chunk == 8) return launch_forward_ch<T, NXL, UP, 8>(sys, trees, items, n_items, ctab, mode, done_out, s);
+  if (mode != kModeAPG)
+    return launch_forward_ch<T, NXL, UP, Chunks<T>::fwd[0], kModeAny>(sys, trees, items, n_items, ctab, mode,
+                                                                       done_out, s);
+  if (chunk == 8)
+    return launch_forward_ch<T, NXL, UP, 8, kModeAPG>(sys, trees, items, n_items, ctab, mode, done_out, s);
   if constexpr (chunk_listed(Chunks<T>::fwd, 16))
-    if (chunk == 16) return launch_forward_ch<T, NXL, UP, 16>(sys, trees, items, n_items, ctab, mode, done_out, s);
+    if (chunk == 16)
+      return launch_forward_ch<T, NXL, UP, 16, kModeAPG>(sys, trees, items, n_items, ctab, mode, done_out, s);
   if constexpr (chunk_listed(Chunks<T>::fwd, 4))
-    if (chunk == 4) return launch_forward_ch<T, NXL, UP, 4>(sys, trees, items, n_items, ctab, mode, done_out, s);
+    if (chunk == 4)
+      return launch_forward_ch<T, NXL, UP, 4, kModeAPG>(sys, trees, items, n_items, ctab, mode, done_out, s);
   return hipErrorInvalidValue;
 }
 

@@ -50,7 +50,7 @@ def test_chunk_length_query_runs_without_a_gpu():
             assert len(lens) >= 1 and len(set(lens)) == len(lens)
             assert all(n in (4, 8, 16, 32) for n in lens)
     # the defaults come first
-    assert smpc.smpc_chunk_lengths(32, 0)[0] == 16 and smpc.smpc_chunk_lengths(64, 1)[0] == 8
+    assert smpc.smpc_chunk_lengths(32, 0)[0] == 16 and smpc.smpc_chunk_lengths(64, 1)[0] == 4
     for bad in ((16, 0), (32, 2)):
         try:
             smpc.smpc_chunk_lengths(*bad)
