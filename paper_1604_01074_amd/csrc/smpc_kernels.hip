@@ -160,6 +160,9 @@ constexpr int kNnzB = 8;   // B rows: a tank is touched by few flows
 // scheduler may not hoist later loads above each batch (with P in registers
 // that would spill).
 constexpr int kLoadBatch = 8;
+// The longest chain whose P product runs on the VALU instead of the matrix
+// cores (a 16-row MFMA tile costs the same for one row as for sixteen).
+constexpr int kValuChain = 4;
 
 template <typename T, int K>
 struct RowCache {
@@ -479,6 +482,32 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
         }
     }
     __syncthreads();  // sRt complete
+    if (ch.len <= kValuChain) {
+      // a short chain (one chunk for every chunk length, so the choice never
+      // depends on the chunk length): du = -P rho / (2 pi) on the VALU from
+      // the same register-resident P.  Lane l of wave w sums its K residue
+      // class, k = 4 st + l / 16, for columns 16 (w NT + t) + l % 16; the four
+      // 16-lane rows are then added, (l, l ^ 16) + (l ^ 32, l ^ 48).
+#pragma unroll
+      for (int cc = 0; cc < kValuChain; ++cc) {
+        if (cc >= C) break;  // wave-uniform
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          T a = T(0);
+#pragma unroll
+          for (int st = 0; st < KS; ++st) {
+            a += preg[st * NT + t] * sRt[(4 * st + (lane >> 4)) * RS + cc];
+            if (st % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+          a += __shfl_xor(a, 16);
+          a += __shfl_xor(a, 32);
+          const int jj = 16 * (wave * NT + t) + (lane & 15);
+          if (lane < 16 && jj < nu) gp(td.du)[(uint32_t)(nb + cc) * (uint32_t)nu + jj] = a * sIp[cc];
+        }
+      }
+      par ^= 1;
+      continue;
+    }
     // du = -P rho / (2 pi) on the matrix cores.  Rows cc >= C of the rho tile
     // hold stale values: they only reach output rows that are not stored.
     v4 acc[MT][NT];
@@ -605,6 +634,13 @@ struct Partials {
   bool nan;           // a NaN met on the way (fmax would drop it)
 };
 
+// An empty asm that takes v in a register: the computation of v stays
+// before this point (an optimisation barrier, no instruction).
+template <typename T>
+__device__ __forceinline__ void pin(T& v) {
+  asm volatile("" : "+v"(v));
+}
+
 __device__ __forceinline__ void fold_max(Partials& p, double hz, double t) {
   const double r = hz - t;
   p.nan |= (r != r);
@@ -659,6 +695,37 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_
     wv[cc] = mode != kModeSolve ? wpoint2(mode, x.c, x.in_scale, yc, yp, n * D + 2 * nx + j) : T(0);
     sv[cc] = x.scaled ? scale[n * 3 + 2] : T(1);
   }
+  if (mode == kModeAPG) {
+    // the recursion, the prox and the dual update of every node, branch-free
+    // (entries past the chunk's end and nodes owned elsewhere are computed,
+    // never stored, and enter the maxima as zeros); only the stores branch
+    T uv[CH], val[CH];
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) {
+      const bool keep = cc < C && chunk_code(cl, cc) < 0;  // wave-uniform
+      if (cc < C) utc += duv[cc];
+      sUp[cc * US + j] = utc;  // rows past the chunk's end are never read
+      const T u = utc + uhv[cc];
+      const T s = sv[cc];
+      const T w = wv[cc];
+      const T a = u + w * (x.ilam / s);  // (w / lambda + s u) / s
+      const T t = clampv(a, ulo, uhi);
+      uv[cc] = u;
+      val[cc] = w + x.lam * s * (u - t);
+      fold_max(pt, keep ? (double)u : 0.0, keep ? (double)t : 0.0);
+      pin(val[cc]);
+    }
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) {
+      if (cc >= C) continue;  // wave-uniform
+      const int32_t code = chunk_code(cl, cc);
+      if (code >= 0) continue;  // wave-uniform: the node is owned elsewhere
+      const uint32_t n = (uint32_t)(-1 - code);
+      if (x.write_z) z[n * W + nx + j] = uv[cc];
+      ynew[n * D + 2 * nx + j] = val[cc];
+    }
+    return;
+  }
 #pragma unroll
   for (int cc = 0; cc < CH; ++cc)
     if (cc < C) {
@@ -690,9 +757,13 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_
 }
 
 // Waves 0 (b = 0, sigma~) and 1 (b = 1, zeta~), one chunk after ut is
-// published: x_n = A x_above + B ut_n + e_n node by node, then the distance
-// prox of block b of owned nodes (the block norm is one wave reduction) and
-// the dual update.
+// published.  Phase A runs x_n = A x_above + B ut_n + e_n for every node of
+// the chunk (with A = I the B ut terms of all nodes are formed first; only
+// the running sum is sequential).  Phase B applies the distance prox of
+// block b to every node at once -- the block norms, square roots and
+// divisions of different nodes are independent, so they overlap -- and
+// stores the dual update and primal output of the owned nodes.  Every value
+// is computed by the same expression as node by node.
 template <typename T, int NXL, int UP, int CH>
 __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T>& x, int b, int32_t cl,
                                                 int C,
@@ -704,36 +775,44 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
   const int lane = threadIdx.x & 63;
   const int nx = sys.nx, nu = sys.nu, D = sys.D;
   const int W = nx + nu;
-  if (!sys.a_identity) {
+  // phase A: the state of every node of the chunk (lanes past nx hold 0)
+  T xs[NXL][CH];
+  if (sys.a_identity) {
+#pragma unroll
+    for (int r = 0; r < NXL; ++r) {
+      const int i = lane + 64 * r;
+      T g[CH];
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) {
+        g[cc] = ev[r][cc];
+        if (brow[r].n <= kNnzB) {
+#pragma unroll
+          for (int q = 0; q < kNnzB; ++q) g[cc] += brow[r].w[q] * sUp[cc * US + brow[r].c[q]];
+        } else {
+          for (int q = brow[r].q0; q < brow[r].q1; ++q) g[cc] += gp(sys.b_v)[q] * sUp[cc * US + gp(sys.b_ci)[q]];
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) {
+        if (cc < C && i < nx) xc[r] += g[cc];
+        xs[r][cc] = i < nx ? xc[r] : T(0);
+      }
+    }
+  } else {
 #pragma unroll
     for (int r = 0; r < NXL; ++r)
       if (lane + 64 * r < nx) cx[lane + 64 * r] = xc[r];
-  }
 #pragma unroll
-  for (int cc = 0; cc < CH; ++cc) {
-    if (cc >= C) continue;  // wave-uniform
-    T xn[NXL];
-    if (sys.a_identity) {
+    for (int cc = 0; cc < CH; ++cc) {
+      if (cc >= C) {  // wave-uniform
 #pragma unroll
-      for (int r = 0; r < NXL; ++r) {
-        const int i = lane + 64 * r;
-        xn[r] = T(0);
-        if (i < nx) {
-          T g = ev[r][cc];
-          if (brow[r].n <= kNnzB) {
-#pragma unroll
-            for (int q = 0; q < kNnzB; ++q) g += brow[r].w[q] * sUp[cc * US + brow[r].c[q]];
-          } else {
-            for (int q = brow[r].q0; q < brow[r].q1; ++q) g += gp(sys.b_v)[q] * sUp[cc * US + gp(sys.b_ci)[q]];
-          }
-          xc[r] += g;
-          xn[r] = xc[r];
-        }
+        for (int r = 0; r < NXL; ++r) xs[r][cc] = T(0);
+        continue;
       }
-    } else {
       // one node at a time; the carry is exchanged through LDS within this
       // wave
       __builtin_amdgcn_wave_barrier();
+      T xn[NXL];
 #pragma unroll
       for (int r = 0; r < NXL; ++r) {
         const int i = lane + 64 * r;
@@ -753,53 +832,83 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
           cx[i] = xn[r];
           xc[r] = xn[r];
         }
+        xs[r][cc] = xn[r];
       }
     }
-    const int32_t code = chunk_code(cl, cc);
-    if (code >= 0) continue;  // wave-uniform: the node is owned elsewhere
-    const uint32_t n = (uint32_t)(-1 - code);
-    if (x.write_z && b == 0) {
+  }
+  if (mode == kModeSolve || mode == kModePower) {
 #pragma unroll
-      for (int r = 0; r < NXL; ++r)
-        if (lane + 64 * r < nx) z[n * W + lane + 64 * r] = xn[r];
-    }
-    if (mode == kModeSolve) continue;
-    const T s = sSP[4 * cc + b];
-    if (mode == kModePower) {
+    for (int cc = 0; cc < CH; ++cc) {
+      if (cc >= C) continue;  // wave-uniform
+      const int32_t code = chunk_code(cl, cc);
+      if (code >= 0) continue;  // wave-uniform: the node is owned elsewhere
+      const uint32_t n = (uint32_t)(-1 - code);
+      if (x.write_z && b == 0) {
+#pragma unroll
+        for (int r = 0; r < NXL; ++r)
+          if (lane + 64 * r < nx) z[n * W + lane + 64 * r] = xs[r][cc];
+      }
+      if (mode == kModeSolve) continue;
+      const T s = sSP[4 * cc + b];
 #pragma unroll
       for (int r = 0; r < NXL; ++r) {
         const int i = lane + 64 * r;
         if (i < nx) {
-          const T g = -s * xn[r];
+          const T g = -s * xs[r][cc];
           ynew[n * D + b * nx + i] = g;
           pt.s0 += (double)g * (double)g;
           pt.s1 += (double)wv[r][cc] * (double)g;
         }
       }
-      continue;
     }
+    return;
+  }
+  // phase B (APG): the prox and the dual update of every node, branch-free
+  // (nodes past the chunk's end and nodes owned elsewhere are computed too,
+  // never stored, and enter the maxima as zeros, which leaves them
+  // unchanged); pin() keeps the compiler from sinking this work into the
+  // per-node store branches below, where it would run node by node
+  T val[NXL][CH];
+#pragma unroll
+  for (int cc = 0; cc < CH; ++cc) {
+    const bool keep = cc < C && chunk_code(cl, cc) < 0;  // wave-uniform
+    const T s = sSP[4 * cc + b];
     const T f = x.ilam / s;
     T a[NXL], pa[NXL];
     T dsq = T(0);
 #pragma unroll
     for (int r = 0; r < NXL; ++r) {
-      a[r] = xn[r] + wv[r][cc] * f;  // (w / lambda + s Hz) / s
+      a[r] = xs[r][cc] + wv[r][cc] * f;  // (w / lambda + s Hz) / s
       pa[r] = b == 0 ? (a[r] > bnd[r][0] ? a[r] : bnd[r][0]) : clampv(a[r], bnd[r][0], bnd[r][1]);
       const T d = lane + 64 * r < nx ? a[r] - pa[r] : T(0);
       dsq += d * d;
     }
     const T del = sqrt(wave_allsum(dsq));
-    const T pin = b == 0 && sys.safety_by_prob ? sSP[4 * cc + 3] : T(1);
-    const T cb = b == 0 ? (T)sys.W_x * pin : (T)sys.gamma_d;
+    const T pi_n = b == 0 && sys.safety_by_prob ? sSP[4 * cc + 3] : T(1);
+    const T cb = b == 0 ? (T)sys.W_x * pi_n : (T)sys.gamma_d;
     const T tau = cb * x.ilam / (s * s);
     const T k = del <= tau ? T(1) : tau / del;
 #pragma unroll
     for (int r = 0; r < NXL; ++r) {
+      const bool in = keep && lane + 64 * r < nx;
+      const T t = del <= tau ? pa[r] : a[r] - k * (a[r] - pa[r]);
+      val[r][cc] = wv[r][cc] + x.lam * s * (xs[r][cc] - t);
+      fold_max(pt, in ? (double)xs[r][cc] : 0.0, in ? (double)t : 0.0);
+      pin(val[r][cc]);
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < CH; ++cc) {
+    if (cc >= C) continue;  // wave-uniform
+    const int32_t code = chunk_code(cl, cc);
+    if (code >= 0) continue;  // wave-uniform: the node is owned elsewhere
+    const uint32_t n = (uint32_t)(-1 - code);
+#pragma unroll
+    for (int r = 0; r < NXL; ++r) {
       const int i = lane + 64 * r;
       if (i < nx) {
-        const T t = del <= tau ? pa[r] : a[r] - k * (a[r] - pa[r]);
-        ynew[n * D + b * nx + i] = wv[r][cc] + x.lam * s * (xn[r] - t);
-        fold_max(pt, (double)xn[r], (double)t);
+        if (x.write_z && b == 0) z[n * W + i] = xs[r][cc];
+        ynew[n * D + b * nx + i] = val[r][cc];
       }
     }
   }
@@ -869,11 +978,12 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
   }
 }
 
-// Two workgroups per CU, except float64 with two state rows per lane and
-// 8-node chunks: that one needs more than 256 registers per lane.
+// Two workgroups per CU, except with two state rows per lane and long
+// chunks (more than 32 bytes of each per-node array per lane): those need
+// more than 256 registers per lane.
 template <typename T, int NXL, int CH>
 constexpr int fwd_min_blocks() {
-  return (sizeof(T) == 8 && NXL > 1 && CH > 4) ? 1 : 2;
+  return (NXL > 1 && CH * sizeof(T) > 32) ? 1 : 2;
 }
 
 template <typename T, int NXL, int UP, int CH, int MODE>
