@@ -71,6 +71,10 @@ def node_bytes(kernel: str, nx: int, nu: int, elem: int, scaled: bool) -> int:
     if kernel.startswith("forward"):
         # du, uhat, e, pi, scale, y^nu, y^{nu-1} -> y^{nu+1}
         return elem * (2 * nu + nx + 1 + sc + 2 * D + D)
+    if kernel.startswith("iter"):
+        # fused launch: the forward rollout of one iteration and the backward
+        # sweep of the next
+        return node_bytes("backward", nx, nu, elem, scaled) + node_bytes("forward", nx, nu, elem, scaled)
     return 0
 
 
@@ -205,8 +209,12 @@ def main() -> int:
     nodes_per_launch = inst.M
     per_node = node_bytes(dom, nx, nu, 8, True)
     achieved = per_node * nodes_per_launch / (avg_ms * 1e-3) / 1e9
-    chunk = r["chunk64"][0 if dom.startswith("backward") else 1]
-    traffic = measured_traffic(f"{dom} chunk {chunk}")
+    if dom.startswith("iter"):
+        chunk = f"{r['chunk64'][0]},{r['chunk64'][1]}"
+        traffic = measured_traffic(f"{dom} chunks {chunk}")
+    else:
+        chunk = r["chunk64"][0 if dom.startswith("backward") else 1]
+        traffic = measured_traffic(f"{dom} chunk {chunk}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom, "chunk": chunk,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": per_node * nodes_per_launch}

@@ -172,7 +172,11 @@ int smpc_tree_info(smpc_tree* tree, int* M, int* N, int* n_chains, int* n_levels
  * after one that warms the pair up; these are ordinary iterations of the
  * solve) and keeps the fastest for the plan and as the system's choice for
  * servers.  A solve whose trees all stop before every pair is timed leaves
- * the plan untuned.                                                        */
+ * the plan untuned.
+ * unfused: 0 -> each APG iteration after the first is one launch (the
+ * forward rollout of iteration nu and the backward sweep of iteration nu + 1
+ * in the same workgroups); 1 -> two launches per iteration (backward, then
+ * forward).  Results are identical.                                         */
 typedef struct {
   double tol;
   int max_iter;
@@ -186,6 +190,7 @@ typedef struct {
   int tune;
   int chunk32[2];
   int chunk64[2];
+  int unfused;
 } smpc_solve_opts;
 
 /* Chunk lengths built into the library for `precision` (32 or 64) and

@@ -411,16 +411,18 @@ template <typename T>
 const char* kname(int which);
 template <>
 const char* kname<double>(int which) {
-  return which == 0 ? "backward_f64" : "forward_f64";
+  return which == 0 ? "backward_f64" : (which == 1 ? "forward_f64" : "iter_f64");
 }
 template <>
 const char* kname<float>(int which) {
-  return which == 0 ? "backward_f32" : "forward_f32";
+  return which == 0 ? "backward_f32" : (which == 1 ? "forward_f32" : "iter_f32");
 }
 
 // Enqueue one iteration of `mode` for every tree of the plan: the backward
 // sweep over all chains, then the forward rollout with prox and the per-tree
-// end of iteration.
+// end of iteration -- or, for fused APG iterations, one launch that runs the
+// forward rollout of this iteration and the backward sweep of the next (the
+// caller has run the backward of the first one, see ensure_backward).
 template <typename T>
 int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode) {
   const SysDev<T>& sv = sysbuf<T>(sys).view;
@@ -428,11 +430,33 @@ int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode) {
   const WorkItem* items = (const WorkItem*)p->items.ptr;
   hipStream_t s = ctx->stream;
   const int* ch = p->chunk[pix<T>()];
+  if (mode == kModeAPG && p->fused) {
+    // forward of this iteration and backward of the next in one launch
+    HIP_TRY(timed(ctx, kname<T>(2), [&] {
+      return launch_iter<T>(sv, td, items, p->n_items, ctx->ctab, ch[0], ch[1], (int32_t*)p->done.ptr, s);
+    }));
+    return SMPC_OK;
+  }
   HIP_TRY(timed(ctx, kname<T>(0),
                 [&] { return launch_backward<T>(sv, td, items, p->n_items, ctx->ctab, mode, ch[0], s); }));
   HIP_TRY(timed(ctx, kname<T>(1), [&] {
     return launch_forward<T>(sv, td, items, p->n_items, ctx->ctab, mode, ch[1], (int32_t*)p->done.ptr, s);
   }));
+  p->bwd_ready[pix<T>()] = false;  // the next iteration starts with its backward
+  return SMPC_OK;
+}
+
+// Before fused APG iterations: the backward of every tree's current
+// iteration (one backward launch, outside any captured graph).
+template <typename T>
+int ensure_backward(smpc_ctx* ctx, smpc_sys* sys, Plan* p) {
+  if (!p->fused || p->bwd_ready[pix<T>()]) return SMPC_OK;
+  const SysDev<T>& sv = sysbuf<T>(sys).view;
+  HIP_TRY(timed(ctx, kname<T>(0), [&] {
+    return launch_backward<T>(sv, plan_td<T>(p), (const WorkItem*)p->items.ptr, p->n_items, ctx->ctab, kModeAPG,
+                              p->chunk[pix<T>()][0], ctx->stream);
+  }));
+  p->bwd_ready[pix<T>()] = true;
   return SMPC_OK;
 }
 
@@ -442,6 +466,7 @@ int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode) {
 // every block of a solve.
 template <typename T>
 int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
+  if (mode == kModeAPG) SMPC_TRY(ensure_backward<T>(ctx, sys, p));
   if (ctx->profiling) {
     for (int k = 0; k < iters; ++k) SMPC_TRY(enqueue_iteration<T>(ctx, sys, p, mode));
     return SMPC_OK;
@@ -451,7 +476,7 @@ int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
     p->graphs_ctab_gen = ctx->ctab_gen;
   }
   const int* ch = p->chunk[pix<T>()];
-  const auto key = std::make_tuple((int)sizeof(T), mode, iters, ch[0], ch[1]);
+  const auto key = std::make_tuple((int)sizeof(T), mode, iters, ch[0], ch[1], (int)(mode == kModeAPG && p->fused));
   auto found = p->graphs.find(key);
   if (found == p->graphs.end()) {
     HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
@@ -471,6 +496,7 @@ int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
     found = p->graphs.emplace(key, exec).first;
   }
   HIP_TRY(hipGraphLaunch(found->second, ctx->stream));
+  if (!(mode == kModeAPG && p->fused)) p->bwd_ready[pix<T>()] = false;
   return SMPC_OK;
 }
 
@@ -839,6 +865,8 @@ int tree_result(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int stat
 
 int run_block_prec(smpc_ctx* ctx, smpc_sys* sys, Plan* p, bool fp32, int iters, bool eager) {
   if (eager) {
+    if (fp32) SMPC_TRY(ensure_backward<float>(ctx, sys, p));
+    else SMPC_TRY(ensure_backward<double>(ctx, sys, p));
     for (int k = 0; k < iters; ++k) {
       if (fp32) SMPC_TRY(enqueue_iteration<float>(ctx, sys, p, kModeAPG));
       else SMPC_TRY(enqueue_iteration<double>(ctx, sys, p, kModeAPG));
@@ -888,6 +916,8 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
   SMPC_TRY(ctx->ensure_ctab(o->max_iter + 2));
   const SolvePhases ph = phases(o);
   choose_chunks(sys, o, false, plan->chunk, plan->tuned);
+  plan->fused = !o->unfused;
+  plan->bwd_ready[0] = plan->bwd_ready[1] = false;  // every tree starts over
   // tuning takes at most 3 blocks per chunk pair (they are iterations too)
   const int max_rounds = o->max_iter / o->check_every + 3 + 3 * 4;
   std::vector<int> fp32_iters(n, 0), status32(n, 0);
@@ -908,6 +938,7 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
       status32[k] = h.status;
       if (ph.run64) SMPC_TRY(tree_to_fp64(plan->trees[k], o, fp32_iters[k], status32[k]));
     }
+    plan->bwd_ready[0] = false;
   }
   if (ph.run64)
     SMPC_TRY(run_until_done<double>(ctx, sys, plan, o->check_every, max_rounds + ph.polish + 2, o->tune != 0));

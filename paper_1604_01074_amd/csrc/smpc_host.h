@@ -166,9 +166,15 @@ struct Plan {
   // [1] float32) and whether they were chosen by timing
   int chunk[2][2] = {{0, 0}, {0, 0}};
   bool tuned[2] = {false, false};
+  // APG iterations as one fused launch each (forward nu + backward nu + 1);
+  // bwd_ready: the backward of every tree's current iteration is done (set
+  // by a backward launch or a fused launch, cleared whenever a tree of the
+  // plan restarts or another mode runs on it)
+  bool fused = true;
+  bool bwd_ready[2] = {false, false};
   // instantiated graphs of `iters` iterations, keyed by (element size, mode,
   // iters, backward chunk, forward chunk)
-  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
+  std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
   int graphs_ctab_gen = -1;
 };
 

@@ -148,6 +148,12 @@ hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const 
 template <typename T>
 hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
                           int n_items, const double* ctab, int mode, int chunk, int32_t* done_out, hipStream_t s);
+// One fused APG iteration (forward of iteration nu, then backward of
+// iteration nu + 1); the launch before the first fused one of a run must be
+// a launch_backward of the APG mode.
+template <typename T>
+hipError_t launch_iter(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+                       const double* ctab, int bchunk, int fchunk, int32_t* done_out, hipStream_t s);
 template <typename T>
 hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s);
 // Warm-start shift: dst0 = dst2 = f * src gathered by node (per dual block

@@ -241,10 +241,10 @@ struct Iter {
 };
 
 template <typename T>
-__device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const G<TreeState>* st, const double* ctab,
-                                             int mode) {
+__device__ __forceinline__ Iter<T> make_iter_at(const TreeDev<T>& td, const G<TreeState>* st, const double* ctab,
+                                                int mode, int it) {
   Iter<T> x;
-  x.it = st->iter;
+  x.it = it;
   x.c = T(0);
   x.in_scale = T(1);
   x.lam = T(1);
@@ -265,11 +265,19 @@ __device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const G<TreeS
   return x;
 }
 
+template <typename T>
+__device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const G<TreeState>* st, const double* ctab,
+                                             int mode) {
+  return make_iter_at(td, st, ctab, mode, (int)st->iter);
+}
+
 // The dual point the solve step is evaluated at: the extrapolated
 // w = y + c (y - y_prev) (APG), the normalised power-iteration vector, or y.
-template <typename T>
+template <typename T, bool AG = false>
 __device__ __forceinline__ T wpoint(const Iter<T>& x, int mode, uint32_t k) {
-  const T y = x.ycur[k];
+  // AG: y^nu was written in this launch by another workgroup (an inner node
+  // of the fused iteration), so it is read at device scope
+  const T y = AG ? __hip_atomic_load(&x.ycur[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : x.ycur[k];
   if (mode == kModeAPG) return y + x.c * (y - x.yprv[k]);
   if (mode == kModePower) return x.in_scale * y;
   return y;
@@ -309,7 +317,7 @@ namespace {
 // held in registers: wave w owns columns [16 NT w, 16 NT (w + 1)) of every
 // 4-row K step).
 // ---------------------------------------------------------------------------
-template <typename T, int KP, int NXL, int CH>
+template <typename T, int KP, int NXL, int CH, bool AG>
 __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode, int chain,
                           unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
                           const RowCache<T, kNnzBt>& bt, int& par) {
@@ -393,7 +401,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
           for (int k = kLoadBatch - 1; k >= 0; --k) {
             const uint32_t n = (uint32_t)(nb + (g + k < C ? g + k : C - 1));
             const T sb = x.scaled ? gp(td.scale)[n * 3 + b] : T(1);
-            xi[k] = sb * wpoint(x, mode, n * D + b * nx + ic);
+            xi[k] = sb * wpoint<T, AG>(x, mode, n * D + b * nx + ic);
           }
 #pragma unroll
           for (int k = kLoadBatch - 1; k >= 0; --k) {
@@ -453,7 +461,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
         for (int k = 0; k < kLoadBatch; ++k) {
           const uint32_t n = (uint32_t)(nb + (g + k < C ? g + k : C - 1));
           const T s2 = x.scaled ? gp(td.scale)[n * 3 + 2] : T(1);
-          rv[k] = (x.affine ? gp(td.beta)[n * nu + j] : T(0)) + s2 * wpoint(x, mode, n * D + 2 * nx + j);
+          rv[k] = (x.affine ? gp(td.beta)[n * nu + j] : T(0)) + s2 * wpoint<T, AG>(x, mode, n * D + 2 * nx + j);
         }
 #pragma unroll
         for (int k = 0; k < kLoadBatch; ++k)
@@ -556,6 +564,60 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
   }
 }
 
+// The register-resident P of this lane (P[4 st + lane / 16][16 (wave NT + t)
+// + lane % 16]), the B' row of an input thread, and the zero rows of the
+// transposed rho tile (they meet the zero rows of P; nothing else writes
+// them).
+template <typename T, int KP, int NXL, int CH>
+__device__ __forceinline__ void bwd_setup(const SysDev<T>& sys, unsigned char* smem_raw, T (&preg)[KP / 4 * (KP / 64)],
+                                          RowCache<T, kNnzBt>& bt) {
+  constexpr int NT = KP / 64, KS = KP / 4;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nu = sys.nu;
+#pragma unroll
+  for (int st = 0; st < KS; ++st)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      preg[st * NT + t] = gp(sys.P)[(size_t)(4 * st + (lane >> 4)) * KP + 16 * (wave * NT + t) + (lane & 15)];
+  load_row(bt, sys.bt_rp, sys.bt_ci, sys.bt_v, tid - 128, wave >= 2 && tid - 128 < nu);
+  T* sRt = reinterpret_cast<T*>(smem_raw) + 2 * CH * 64 * NXL;
+  for (int e = tid; e < (KP - nu) * (CH + 1); e += kBlock) sRt[(size_t)nu * (CH + 1) + e] = T(0);
+}
+
+// The backward sweep of one leaf chain, then of each ancestor chain whose
+// children have all been swept (the workgroup that completes a parent's
+// count sweeps it).  AGP: the ancestors' y^nu was written in this launch by
+// other workgroups and is read at device scope.
+template <typename T, int KP, int NXL, int CH, bool AGP>
+__device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode,
+                                         int leaf, unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
+                                         const RowCache<T, kNnzBt>& bt, int& par, int& s_last) {
+  const int tid = threadIdx.x;
+  int chain = leaf;
+  while (true) {
+    if (AGP && chain != leaf)
+      bwd_chain<T, KP, NXL, CH, true>(sys, td, x, mode, chain, smem_raw, preg, bt, par);
+    else
+      bwd_chain<T, KP, NXL, CH, false>(sys, td, x, mode, chain, smem_raw, preg, bt, par);
+    const int parent = gp(td.chains)[chain].parent;
+    if (parent < 0) break;  // the root chain is done: the sweep is complete
+    // this chain's top terms are stored: count this child done at the parent
+    wait_mem();
+    __syncthreads();
+    if (tid == 0) {
+      const int pc = gp(td.chains)[parent].child_count;
+      const int prev = __hip_atomic_fetch_add(gp(td.cnt) + parent, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_last = (prev == pc - 1);
+      if (s_last) __hip_atomic_store(gp(td.cnt) + parent, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next iteration
+    }
+    __syncthreads();
+    if (!s_last) break;  // a sibling is still running; it will sweep the parent
+    chain = parent;
+  }
+}
+
 // Persistent: workgroup b takes leaf chains b, b + gridDim.x, ... (longest
 // first), so the register-resident P is loaded once per workgroup.
 template <typename T, int KP, int NXL, int CH, int MODE>
@@ -566,52 +628,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_last;
   constexpr int NT = KP / 64, KS = KP / 4;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int nu = sys.nu;
-
-  // this lane's P entries: P[4 st + lane / 16][16 (wave NT + t) + lane % 16]
   T preg[KS * NT];
-#pragma unroll
-  for (int st = 0; st < KS; ++st)
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-      preg[st * NT + t] = gp(sys.P)[(size_t)(4 * st + (lane >> 4)) * KP + 16 * (wave * NT + t) + (lane & 15)];
   RowCache<T, kNnzBt> bt;
-  load_row(bt, sys.bt_rp, sys.bt_ci, sys.bt_v, tid - 128, wave >= 2 && tid - 128 < nu);
-  {
-    // padded rows of the transposed rho tile must be finite (they meet the
-    // zero rows of P); nothing else writes them
-    T* sRt = reinterpret_cast<T*>(smem_raw) + 2 * CH * 64 * NXL;
-    for (int e = tid; e < (KP - nu) * (CH + 1); e += kBlock) sRt[(size_t)nu * (CH + 1) + e] = T(0);
-  }
+  bwd_setup<T, KP, NXL, CH>(sys, smem_raw, preg, bt);
   int par = 0;
-
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const WorkItem wi = items[item];
     const TreeDev<T>& td = trees[wi.tree];
     const G<TreeState>* st = gp(td.st);
     if (st->done) continue;
     const Iter<T> x = make_iter(td, st, ctab, mode);
-    int chain = wi.chain;
-    while (true) {
-      bwd_chain<T, KP, NXL, CH>(sys, td, x, mode, chain, smem_raw, preg, bt, par);
-      const int parent = gp(td.chains)[chain].parent;
-      if (parent < 0) break;  // the root chain is done: the sweep is complete
-      // this chain's top terms are stored: count this child done at the parent
-      wait_mem();
-      __syncthreads();
-      if (tid == 0) {
-        const int pc = gp(td.chains)[parent].child_count;
-        const int prev = __hip_atomic_fetch_add(gp(td.cnt) + parent, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == pc - 1);
-        if (s_last) __hip_atomic_store(gp(td.cnt) + parent, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next iteration
-      }
-      __syncthreads();
-      if (!s_last) break;  // a sibling is still running; it will sweep the parent
-      chain = parent;
-    }
+    bwd_item<T, KP, NXL, CH, false>(sys, td, x, mode, wi.chain, smem_raw, preg, bt, par, s_last);
   }
 }
 
@@ -633,6 +660,17 @@ struct Partials {
   double s0, s1, s2;  // residual / |Hz| / |t| maxima, or power-iteration sums
   bool nan;           // a NaN met on the way (fmax would drop it)
 };
+
+// Store of a dual entry: AG and an inner node (an ancestor chain's node,
+// read later in the same fused launch by the workgroup that sweeps that
+// chain) -> device scope; otherwise a plain store.
+template <typename T, bool AG>
+__device__ __forceinline__ void put_dual(G<T>* p, T v, bool inner) {
+  if (AG && inner)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
 
 // An empty asm that takes v in a register: the computation of v stays
 // before this point (an optimisation barrier, no instruction).
@@ -673,9 +711,9 @@ __device__ __forceinline__ int32_t chunk_code(int32_t cl, int cc) { return __bui
 // of the psi~ blocks and the dual update.  The arrays are distinct
 // allocations (the three dual slots rotate), so the loads of later nodes may
 // be issued before the stores of earlier ones.
-template <typename T, int UP, int CH>
-__device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_t cl, int C, int j, int nx, int nu,
-                                              int D,
+template <typename T, int UP, int CH, bool AG>
+__device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_t cl, int C, int npath, int j, int nx,
+                                              int nu, int D,
                                               const G<T>* __restrict__ du, const G<T>* __restrict__ uhat,
                                               const G<T>* __restrict__ yc, const G<T>* __restrict__ yp,
                                               const G<T>* __restrict__ scale, G<T>* __restrict__ ynew,
@@ -722,7 +760,7 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_
       if (code >= 0) continue;  // wave-uniform: the node is owned elsewhere
       const uint32_t n = (uint32_t)(-1 - code);
       if (x.write_z) z[n * W + nx + j] = uv[cc];
-      ynew[n * D + 2 * nx + j] = val[cc];
+      put_dual<T, AG>(&ynew[n * D + 2 * nx + j], val[cc], cc < npath);
     }
     return;
   }
@@ -764,9 +802,9 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_
 // divisions of different nodes are independent, so they overlap -- and
 // stores the dual update and primal output of the owned nodes.  Every value
 // is computed by the same expression as node by node.
-template <typename T, int NXL, int UP, int CH>
+template <typename T, int NXL, int UP, int CH, bool AG>
 __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T>& x, int b, int32_t cl,
-                                                int C,
+                                                int C, int npath,
                                                 const T (&ev)[NXL][CH], const T (&wv)[NXL][CH],
                                                 const RowCache<T, kNnzB> (&brow)[NXL], const T (&bnd)[NXL][2],
                                                 const T* sSP, G<T>* __restrict__ ynew, G<T>* __restrict__ z,
@@ -908,13 +946,13 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
       const int i = lane + 64 * r;
       if (i < nx) {
         if (x.write_z && b == 0) z[n * W + i] = xs[r][cc];
-        ynew[n * D + b * nx + i] = val[r][cc];
+        put_dual<T, AG>(&ynew[n * D + b * nx + i], val[r][cc], cc < npath);
       }
     }
   }
 }
 
-template <typename T, int NXL, int UP, int CH>
+template <typename T, int NXL, int UP, int CH, bool AG>
 __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode,
                           const G<int32_t>* codes, int plen, int first, int len, unsigned char* smem_raw,
                           const RowCache<T, kNnzB> (&brow)[NXL], T (&xc)[NXL], T& utc, const T (&bnd)[NXL][2],
@@ -936,6 +974,7 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
   int32_t cl = node_code(codes, plen, first, lane < last ? lane : last);
   for (int k0 = 0; k0 < len; k0 += CH) {
     const int C = len - k0 < CH ? len - k0 : CH;
+    const int npath = plen - k0;  // entries cc < npath are ancestor (inner) nodes
     const int32_t cur = cl;
     if (k0 + CH < len) cl = node_code(codes, plen, first, k0 + CH + lane < last ? k0 + CH + lane : last);
     T* sUp = sU + par * CH * UP;
@@ -948,7 +987,7 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
       sSPp[4 * tid + 3] = gp(td.pi)[n];
     }
     if (ju)
-      fwd_psi_chunk<T, UP, CH>(mode, x, cur, C, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur, x.yprv,
+      fwd_psi_chunk<T, UP, CH, AG>(mode, x, cur, C, npath, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur, x.yprv,
                                gp(td.scale), x.ynew, gp(td.z), sUp, utc, ubnd[0], ubnd[1], pt);
     // waves 0, 1: e and the dual point of the wave's block, loaded before the
     // barrier, unconditionally (a node owned elsewhere loads a value it does
@@ -972,7 +1011,7 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
     }
     __syncthreads();  // ut of the chunk published
     if (wave < 2)
-      fwd_state_chunk<T, NXL, UP, CH>(sys, mode, x, b, cur, C, ev, wv, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
+      fwd_state_chunk<T, NXL, UP, CH, AG>(sys, mode, x, b, cur, C, npath, ev, wv, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
                                       sXc + (size_t)wave * nx, xc, pt);
     par ^= 1;
   }
@@ -986,25 +1025,18 @@ constexpr int fwd_min_blocks() {
   return (NXL > 1 && CH * sizeof(T) > 32) ? 1 : 2;
 }
 
-template <typename T, int NXL, int UP, int CH, int MODE>
-__global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
-                                                       const WorkItem* __restrict__ items,
-                                                       const double* __restrict__ ctab, int mode_arg,
-                                                       int32_t* __restrict__ done_out) {
-  const int mode = MODE == kModeAny ? mode_arg : MODE;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int s_last;
+// The forward rollout and prox of one leaf chain (with its root path), its
+// residual partials, and -- in the tree's last workgroup -- the end of the
+// iteration (stop test, counters).  AG: the ancestors' dual entries this
+// chain owns are stored at device scope (the fused iteration reads them in
+// the same launch).
+template <typename T, int NXL, int UP, int CH, bool AG>
+__device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const TreeDev<T>& td, const WorkItem wi,
+                                         G<TreeState>* st, const Iter<T>& x, int mode, unsigned char* smem_raw,
+                                         int& s_last, int32_t* __restrict__ done_out) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const WorkItem wi = items[blockIdx.x];
-  const TreeDev<T>& td = trees[wi.tree];
-  G<TreeState>* st = gp(td.st);
-  if (st->done) {
-    if (tid == 0) done_out[wi.tree] = 1;
-    return;
-  }
-  const Iter<T> x = make_iter(td, st, ctab, mode);
   const int nx = sys.nx, nu = sys.nu;
   const int j = tid - 128;
   double* sRed = reinterpret_cast<double*>(smem_raw + lds_bytes_forward(nx, nu, sizeof(T), CH) - 32 * sizeof(double));
@@ -1033,7 +1065,7 @@ __global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forw
   // chain itself, as one sequence
   const int p0 = gp(td.path_off)[wi.chain], p1 = gp(td.path_off)[wi.chain + 1];
   const ChainDesc ch = gp(td.chains)[wi.chain];
-  fwd_nodes<T, NXL, UP, CH>(sys, td, x, mode, gp(td.path) + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw, brow, xc,
+  fwd_nodes<T, NXL, UP, CH, AG>(sys, td, x, mode, gp(td.path) + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw, brow, xc,
                         utc, bnd, ubnd, par, pt);
 
   // partials of this leaf chain
@@ -1148,6 +1180,64 @@ __global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forw
       done_out[wi.tree] = 0;
     }
   }
+}
+
+
+template <typename T, int NXL, int UP, int CH, int MODE>
+__global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
+                                                       const WorkItem* __restrict__ items,
+                                                       const double* __restrict__ ctab, int mode_arg,
+                                                       int32_t* __restrict__ done_out) {
+  const int mode = MODE == kModeAny ? mode_arg : MODE;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_last;
+  const WorkItem wi = items[blockIdx.x];
+  const TreeDev<T>& td = trees[wi.tree];
+  G<TreeState>* st = gp(td.st);
+  if (st->done) {
+    if (threadIdx.x == 0) done_out[wi.tree] = 1;
+    return;
+  }
+  const Iter<T> x = make_iter(td, st, ctab, mode);
+  fwd_item<T, NXL, UP, CH, false>(sys, td, wi, st, x, mode, smem_raw, s_last, done_out);
+}
+
+// One fused APG iteration: the forward rollout of iteration nu for a leaf
+// chain, then the backward sweep of iteration nu + 1 for the same chain (its
+// y^{nu+1} was written just before by this workgroup) and for each ancestor
+// chain this workgroup completes.  The launch before the first fused one of
+// a run is a backward launch.  A tree that stops at iteration nu has swept
+// iteration nu + 1 for nothing; nothing reads it.
+// The fused kernel holds the backward kernel's registers too: with two
+// state rows per lane and 128-wide float64 P it runs one workgroup per CU.
+template <typename T, int KP, int NXL, int FCH>
+constexpr int iter_min_blocks() {
+  return (fwd_min_blocks<T, NXL, FCH>() == 1 || (NXL > 1 && sizeof(T) == 8 && KP == 128)) ? 1 : 2;
+}
+
+template <typename T, int KP, int NXL, int BCH, int FCH>
+__global__ __launch_bounds__(kBlock, (iter_min_blocks<T, KP, NXL, FCH>())) void k_iter(
+    SysDev<T> sys, const TreeDev<T>* __restrict__ trees, const WorkItem* __restrict__ items,
+    const double* __restrict__ ctab, int32_t* __restrict__ done_out) {
+  constexpr int NT = KP / 64, KS = KP / 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_last;
+  const WorkItem wi = items[blockIdx.x];
+  const TreeDev<T>& td = trees[wi.tree];
+  G<TreeState>* st = gp(td.st);
+  if (st->done) {
+    if (threadIdx.x == 0) done_out[wi.tree] = 1;
+    return;
+  }
+  const Iter<T> xf = make_iter(td, st, ctab, kModeAPG);
+  fwd_item<T, NXL, KP, FCH, true>(sys, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out);
+  __syncthreads();  // the LDS now holds the backward layout
+  const Iter<T> xb = make_iter_at(td, st, ctab, kModeAPG, xf.it + 1);
+  T preg[KS * NT];
+  RowCache<T, kNnzBt> bt;
+  bwd_setup<T, KP, NXL, BCH>(sys, smem_raw, preg, bt);
+  int par = 0;
+  bwd_item<T, KP, NXL, BCH, true>(sys, td, xb, kModeAPG, wi.chain, smem_raw, preg, bt, par, s_last);
 }
 
 template <typename T>
@@ -1289,6 +1379,57 @@ hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const W
   return u1 ? launch_forward_t<T, 2, 64>(sys, trees, items, n_items, ctab, mode, chunk, done_out, s)
             : launch_forward_t<T, 2, 128>(sys, trees, items, n_items, ctab, mode, chunk, done_out, s);
 }
+
+template <typename T, int KP, int NXL, int BCH, int FCH>
+hipError_t launch_iter_ch(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+                          const double* ctab, int32_t* done_out, hipStream_t s) {
+  const size_t lds = std::max(lds_bytes_forward(sys.nx, sys.nu, sizeof(T), FCH),
+                              lds_bytes_backward(sys.nx, sys.nu, sizeof(T), BCH));
+  hipError_t e = allow_lds(k_iter<T, KP, NXL, BCH, FCH>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_iter<T, KP, NXL, BCH, FCH>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab,
+                     done_out);
+  return hipGetLastError();
+}
+
+template <typename T, int KP, int NXL, int BCH>
+hipError_t launch_iter_b(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+                         const double* ctab, int fchunk, int32_t* done_out, hipStream_t s) {
+  if (fchunk == 8) return launch_iter_ch<T, KP, NXL, BCH, 8>(sys, trees, items, n_items, ctab, done_out, s);
+  if constexpr (chunk_listed(Chunks<T>::fwd, 16))
+    if (fchunk == 16) return launch_iter_ch<T, KP, NXL, BCH, 16>(sys, trees, items, n_items, ctab, done_out, s);
+  if constexpr (chunk_listed(Chunks<T>::fwd, 4))
+    if (fchunk == 4) return launch_iter_ch<T, KP, NXL, BCH, 4>(sys, trees, items, n_items, ctab, done_out, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int KP, int NXL>
+hipError_t launch_iter_kp(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+                          const double* ctab, int bchunk, int fchunk, int32_t* done_out, hipStream_t s) {
+  if (bchunk == 16) return launch_iter_b<T, KP, NXL, 16>(sys, trees, items, n_items, ctab, fchunk, done_out, s);
+  if constexpr (chunk_listed(Chunks<T>::bwd, 32))
+    if (bchunk == 32) return launch_iter_b<T, KP, NXL, 32>(sys, trees, items, n_items, ctab, fchunk, done_out, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_iter(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+                       const double* ctab, int bchunk, int fchunk, int32_t* done_out, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (sys.nx > 128 || sys.nu > 128 || !chunk_listed(Chunks<T>::bwd, bchunk) || !chunk_listed(Chunks<T>::fwd, fchunk))
+    return hipErrorInvalidValue;
+  const bool x1 = sys.nx <= 64;
+  if (sys.nu <= 64)
+    return x1 ? launch_iter_kp<T, 64, 1>(sys, trees, items, n_items, ctab, bchunk, fchunk, done_out, s)
+              : launch_iter_kp<T, 64, 2>(sys, trees, items, n_items, ctab, bchunk, fchunk, done_out, s);
+  return x1 ? launch_iter_kp<T, 128, 1>(sys, trees, items, n_items, ctab, bchunk, fchunk, done_out, s)
+            : launch_iter_kp<T, 128, 2>(sys, trees, items, n_items, ctab, bchunk, fchunk, done_out, s);
+}
+
+template hipError_t launch_iter<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
+                                        const double*, int, int, int32_t*, hipStream_t);
+template hipError_t launch_iter<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
+                                       const double*, int, int, int32_t*, hipStream_t);
 
 template <typename T>
 hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s) {

@@ -56,6 +56,7 @@ struct smpc_server {
   smpc_solve_opts o{};
   int max_active = 0;
   int chunk[2][2] = {{0, 0}, {0, 0}};  // chunk lengths of its launch groups ([0] float64, [1] float32)
+  bool restarted[2] = {false, false};  // a tree of launch group g (0 float32, 1 float64) started over
   std::thread worker;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -115,6 +116,7 @@ int sync_group(smpc_server* S, int g) {
   SMPC_TRY(plan_build(ctx, want, g == 0, &S->group[g]));
   for (int k = 0; k < 2; ++k)
     for (int w = 0; w < 2; ++w) S->group[g]->chunk[k][w] = S->chunk[k][w];
+  S->group[g]->fused = !S->o.unfused;
   return SMPC_OK;
 }
 
@@ -161,10 +163,16 @@ void worker_main(smpc_server* S) {
       r->phase = ph.run32 ? 32 : 64;
       S->active.push_back(r);
     }
+    if (!start.empty()) S->restarted[ph.run32 ? 0 : 1] = true;
     if (S->active.empty()) continue;
     int rc = SMPC_OK;
     for (int g = 0; g < 2 && rc >= 0; ++g) {
       rc = sync_group(S, g);
+      if (rc >= 0 && S->group[g] && S->restarted[g]) {
+        // a tree of the group started over: its current backward is not done
+        S->group[g]->bwd_ready[0] = S->group[g]->bwd_ready[1] = false;
+      }
+      S->restarted[g] = false;
       if (rc >= 0 && S->group[g]) rc = run_block_prec(ctx, S->sys, S->group[g], g == 0, S->o.check_every, true);
     }
     for (int g = 0; g < 2 && rc >= 0; ++g)
@@ -197,6 +205,7 @@ void worker_main(smpc_server* S) {
             code = tree_to_fp64(r->t, &S->o, r->fp32_iters, r->status32);
             if (code >= 0) {
               r->phase = 64;
+              S->restarted[1] = true;
               still.push_back(r);
               continue;
             }

@@ -82,7 +82,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("precision", C.c_int), ("polish_iters", C.c_int), ("warm_start", C.c_int),
                 ("y0", _dp), ("y_prev0", _dp), ("stall_checks", C.c_int), ("tune", C.c_int),
-                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2)]
+                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2), ("unfused", C.c_int)]
 
 
 class Result(C.Structure):
@@ -256,14 +256,14 @@ def _pair(v):
 
 
 def _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks=0, resident=False,
-          tune=0, chunk32=None, chunk64=None):
+          tune=0, chunk32=None, chunk64=None, unfused=False):
     keep = [None if y0 is None else _f64(y0), None if y_prev0 is None else _f64(y_prev0)]
     if resident and y0 is not None:
         raise ValueError("a resident warm start and y0 exclude each other")
     warm = 1 if resident else (2 if y0 is not None else 0)
     o = SolveOpts(float(tol), int(max_iter), int(check_every), int(precision), int(polish_iters),
                   warm, _ptr(keep[0]), _ptr(keep[1]), int(stall_checks), int(tune), _pair(chunk32),
-                  _pair(chunk64))
+                  _pair(chunk64), int(bool(unfused)))
     return o, keep
 
 
@@ -287,12 +287,12 @@ def _finish(r: Result, out: dict) -> dict:
 
 def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precision=64, polish_iters=0,
                y0=None, y_prev0=None, want_x=True, want_y=True, stall_checks=0, resident=False, tune=0,
-               chunk32=None, chunk64=None) -> dict:
+               chunk32=None, chunk64=None, unfused=False) -> dict:
     """``dims = (M, nx, nu)``.  Returns a dict with u0, x, u, y, iterations,
     fp32_iterations, r_primal, hz_t_max, status, chunk32, chunk64."""
     M, nx, nu = dims
     o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident,
-                    tune, chunk32, chunk64)
+                    tune, chunk32, chunk64, unfused)
     r, out = _result(M, nx, nu, want_x, want_y)
     pp, qq = _f64(p), _f64(q)
     _check_solve(_lib.smpc_solve(t, _ptr(pp), _ptr(qq), C.byref(o), C.byref(r)))
@@ -301,10 +301,11 @@ def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precis
 
 def smpc_solve_batch(trees, ps, qs, *, dims_list, tol=1e-3, max_iter=1000, check_every=10, precision=64,
                      polish_iters=0, y0=None, y_prev0=None, want_x=True, want_y=True,
-                     stall_checks=0, resident=False, tune=0, chunk32=None, chunk64=None) -> tuple[int, list]:
+                     stall_checks=0, resident=False, tune=0, chunk32=None, chunk64=None,
+                     unfused=False) -> tuple[int, list]:
     n = len(trees)
     o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident,
-                    tune, chunk32, chunk64)
+                    tune, chunk32, chunk64, unfused)
     res = (Result * n)()
     outs = []
     for k, (M, nx, nu) in enumerate(dims_list):
@@ -364,9 +365,9 @@ def smpc_ctx_reset_stats(ctx) -> None:
 # ---------------------------------------------------------------- serving
 
 def smpc_server_create(sys_handle, *, tol=1e-3, max_iter=1000, check_every=10, precision=32, polish_iters=20,
-                       stall_checks=0, max_active=0, tune=0, chunk32=None, chunk64=None):
+                       stall_checks=0, max_active=0, tune=0, chunk32=None, chunk64=None, unfused=False):
     o, _ = _opts(tol, max_iter, check_every, precision, polish_iters, None, None, stall_checks, False, tune,
-                 chunk32, chunk64)
+                 chunk32, chunk64, unfused)
     so = ServerOpts(o, int(max_active))
     h = _vp()
     _check(_lib.smpc_server_create(sys_handle, C.byref(so), C.byref(h)))
