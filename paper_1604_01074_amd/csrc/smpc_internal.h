@@ -139,8 +139,9 @@ constexpr bool chunk_listed(const int (&a)[N], int v) {
 
 // Kernel launchers (smpc_kernels.hip).  `items` lists the leaf chains of all
 // trees of the launch; `trees` is a device table.  One iteration is
-// launch_backward then launch_forward; `done_out[tree]` receives each tree's
-// stop flag at the end of the forward kernel.  `chunk` must be listed in
+// launch_backward then launch_forward (or, after one launch_backward, one
+// launch_iter per iteration); `done_out[tree]` receives each tree's stop flag
+// at the end of the forward rollout.  `chunk` must be listed in
 // Chunks<T> (hipErrorInvalidValue otherwise).
 template <typename T>
 hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
