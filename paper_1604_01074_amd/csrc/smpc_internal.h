@@ -163,9 +163,25 @@ template <typename Ts, typename Td>
 hipError_t launch_shift(const Ts* src, Td* dst0, Td* dst2, const int32_t* src_node, const double* f, int M,
                         int nx, int nu, hipStream_t s);
 
-// Row stride of the zero-padded P on the device (and of the staged rho rows).
-__host__ __device__ int p_stride(int nu);
-__host__ __device__ size_t lds_bytes_backward(int nx, int nu, size_t elem, int chunk);
-__host__ __device__ size_t lds_bytes_forward(int nx, int nu, size_t elem, int chunk);
+// Row stride of the zero-padded P on the device (and of the staged rho rows),
+// and the dynamic LDS of the two kernels.
+__host__ __device__ inline int p_stride(int nu) { return nu <= 64 ? 64 : 128; }
+
+__host__ __device__ inline size_t lds_bytes_backward(int nx, int nu, size_t elem, int chunk) {
+  // the two Q parts of the chunk (2 x chunk x padded nx), rho transposed (P-stride
+  // rows of chunk + 1 entries), -1/(2 pi) for two chunks, two Q carries
+  // (general A), the chain-top exchange
+  const size_t ch = (size_t)chunk;
+  const size_t xs = nx <= 64 ? 64 : 128;
+  return elem * (2 * ch * xs + (size_t)p_stride(nu) * (ch + 1) + 2 * ch + 3 * (size_t)nx);
+}
+
+__host__ __device__ inline size_t lds_bytes_forward(int nx, int nu, size_t elem, int chunk) {
+  // ut of two chunks (2 x chunk x padded nu), scales and pi of two chunks,
+  // the x carries of waves 0 and 1 (general A), 32 float64 reduction slots
+  const size_t ch = (size_t)chunk;
+  return elem * (2 * ch * (size_t)p_stride(nu) + 8 * ch + 2 * (size_t)nx) + 32 * sizeof(double);
+}
+
 
 }  // namespace smpc

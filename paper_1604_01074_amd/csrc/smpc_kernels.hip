@@ -28,7 +28,14 @@
 //   ut_n = ut_{a(n)} + du_n,  u_n = ut_n + uhat_n,  x_n = A x_{a(n)} + B ut_n + e_n
 // which is Alg. 1 multiplied through by L (du_n = L dv_n, ut_n = L v_n).
 // B and A are applied in sparse form; P is held in registers.
+// The library builds this file once (SMPC_KERNEL_PART undefined, every
+// instantiation) or twice in parallel: part 1 holds the float64 kernels and
+// the mixed-precision helpers, part 2 the float32 kernels.
 #include "smpc_internal.h"
+
+#ifndef SMPC_KERNEL_PART
+#define SMPC_KERNEL_PART 0
+#endif
 
 #include <algorithm>
 #include <map>
@@ -284,24 +291,6 @@ __device__ __forceinline__ T wpoint(const Iter<T>& x, int mode, uint32_t k) {
 }
 
 }  // namespace
-
-__host__ __device__ int p_stride(int nu) { return nu <= 64 ? 64 : 128; }
-
-__host__ __device__ size_t lds_bytes_backward(int nx, int nu, size_t elem, int chunk) {
-  // the two Q parts of the chunk (2 x chunk x padded nx), rho transposed (P-stride
-  // rows of chunk + 1 entries), -1/(2 pi) for two chunks, two Q carries
-  // (general A), the chain-top exchange
-  const size_t ch = (size_t)chunk;
-  const size_t xs = nx <= 64 ? 64 : 128;
-  return elem * (2 * ch * xs + (size_t)p_stride(nu) * (ch + 1) + 2 * ch + 3 * (size_t)nx);
-}
-
-__host__ __device__ size_t lds_bytes_forward(int nx, int nu, size_t elem, int chunk) {
-  // ut of two chunks (2 x chunk x padded nu), scales and pi of two chunks,
-  // the x carries of waves 0 and 1 (general A), 32 float64 reduction slots
-  const size_t ch = (size_t)chunk;
-  return elem * (2 * ch * (size_t)p_stride(nu) + 8 * ch + 2 * (size_t)nx) + 32 * sizeof(double);
-}
 
 namespace {
 
@@ -1426,10 +1415,14 @@ hipError_t launch_iter(const SysDev<T>& sys, const TreeDev<T>* trees, const Work
             : launch_iter_kp<T, 128, 2>(sys, trees, items, n_items, ctab, bchunk, fchunk, done_out, s);
 }
 
+#if SMPC_KERNEL_PART != 2
 template hipError_t launch_iter<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
                                         const double*, int, int, int32_t*, hipStream_t);
+#endif
+#if SMPC_KERNEL_PART != 1
 template hipError_t launch_iter<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
                                        const double*, int, int, int32_t*, hipStream_t);
+#endif
 
 template <typename T>
 hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s) {
@@ -1439,15 +1432,19 @@ hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+#if SMPC_KERNEL_PART != 2
 template hipError_t launch_backward<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
                                             const double*, int, int, hipStream_t);
-template hipError_t launch_backward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
-                                           const double*, int, int, hipStream_t);
 template hipError_t launch_forward<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
                                            const double*, int, int, int32_t*, hipStream_t);
+template hipError_t launch_widen<float>(const float*, double*, size_t, hipStream_t);
+#endif
+#if SMPC_KERNEL_PART != 1
+template hipError_t launch_backward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
+                                           const double*, int, int, hipStream_t);
 template hipError_t launch_forward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
                                           const double*, int, int, int32_t*, hipStream_t);
-template hipError_t launch_widen<float>(const float*, double*, size_t, hipStream_t);
+#endif
 
 template <typename Ts, typename Td>
 hipError_t launch_shift(const Ts* src, Td* dst0, Td* dst2, const int32_t* src_node, const double* f, int M,
@@ -1459,6 +1456,7 @@ hipError_t launch_shift(const Ts* src, Td* dst0, Td* dst2, const int32_t* src_no
   return hipGetLastError();
 }
 
+#if SMPC_KERNEL_PART != 2
 template hipError_t launch_shift<double, double>(const double*, double*, double*, const int32_t*, const double*,
                                                  int, int, int, hipStream_t);
 template hipError_t launch_shift<double, float>(const double*, float*, float*, const int32_t*, const double*, int,
@@ -1467,5 +1465,6 @@ template hipError_t launch_shift<float, double>(const float*, double*, double*, 
                                                 int, int, hipStream_t);
 template hipError_t launch_shift<float, float>(const float*, float*, float*, const int32_t*, const double*, int,
                                                int, int, hipStream_t);
+#endif
 
 }  // namespace smpc
