@@ -134,7 +134,7 @@ def main() -> int:
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X and has no multi-GPU path "
-              "(see DESIGN.md for how it would shard).", file=sys.stderr)
+              "(trees would shard across GPUs whole, with no per-iteration exchange).", file=sys.stderr)
         return 2
 
     import torch
