@@ -554,25 +554,29 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
 }
 
 // The register-resident P of this lane (P[4 st + lane / 16][16 (wave NT + t)
-// + lane % 16]), the B' row of an input thread, and the zero rows of the
-// transposed rho tile (they meet the zero rows of P; nothing else writes
-// them).
-template <typename T, int KP, int NXL, int CH>
-__device__ __forceinline__ void bwd_setup(const SysDev<T>& sys, unsigned char* smem_raw, T (&preg)[KP / 4 * (KP / 64)],
-                                          RowCache<T, kNnzBt>& bt) {
+// + lane % 16]) and the B' row of an input thread; then, in LDS, the zero
+// rows of the transposed rho tile (they meet the zero rows of P; nothing
+// else writes them).
+template <typename T, int KP>
+__device__ __forceinline__ void bwd_load_regs(const SysDev<T>& sys, T (&preg)[KP / 4 * (KP / 64)],
+                                              RowCache<T, kNnzBt>& bt) {
   constexpr int NT = KP / 64, KS = KP / 4;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int nu = sys.nu;
 #pragma unroll
   for (int st = 0; st < KS; ++st)
 #pragma unroll
     for (int t = 0; t < NT; ++t)
       preg[st * NT + t] = gp(sys.P)[(size_t)(4 * st + (lane >> 4)) * KP + 16 * (wave * NT + t) + (lane & 15)];
-  load_row(bt, sys.bt_rp, sys.bt_ci, sys.bt_v, tid - 128, wave >= 2 && tid - 128 < nu);
+  load_row(bt, sys.bt_rp, sys.bt_ci, sys.bt_v, tid - 128, wave >= 2 && tid - 128 < sys.nu);
+}
+
+template <typename T, int KP, int NXL, int CH>
+__device__ __forceinline__ void bwd_zero_rows(const SysDev<T>& sys, unsigned char* smem_raw) {
+  const int nu = sys.nu;
   T* sRt = reinterpret_cast<T*>(smem_raw) + 2 * CH * 64 * NXL;
-  for (int e = tid; e < (KP - nu) * (CH + 1); e += kBlock) sRt[(size_t)nu * (CH + 1) + e] = T(0);
+  for (int e = threadIdx.x; e < (KP - nu) * (CH + 1); e += kBlock) sRt[(size_t)nu * (CH + 1) + e] = T(0);
 }
 
 // The backward sweep of one leaf chain, then of each ancestor chain whose
@@ -619,7 +623,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
   constexpr int NT = KP / 64, KS = KP / 4;
   T preg[KS * NT];
   RowCache<T, kNnzBt> bt;
-  bwd_setup<T, KP, NXL, CH>(sys, smem_raw, preg, bt);
+  bwd_load_regs<T, KP>(sys, preg, bt);
+  bwd_zero_rows<T, KP, NXL, CH>(sys, smem_raw);
   int par = 0;
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const WorkItem wi = items[item];
@@ -1019,10 +1024,10 @@ constexpr int fwd_min_blocks() {
 // iteration (stop test, counters).  AG: the ancestors' dual entries this
 // chain owns are stored at device scope (the fused iteration reads them in
 // the same launch).
-template <typename T, int NXL, int UP, int CH, bool AG>
+template <typename T, int NXL, int UP, int CH, bool AG, typename AfterRollout>
 __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const TreeDev<T>& td, const WorkItem wi,
                                          G<TreeState>* st, const Iter<T>& x, int mode, unsigned char* smem_raw,
-                                         int& s_last, int32_t* __restrict__ done_out) {
+                                         int& s_last, int32_t* __restrict__ done_out, AfterRollout after_rollout) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -1057,6 +1062,7 @@ __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const TreeDev<T>&
   fwd_nodes<T, NXL, UP, CH, AG>(sys, td, x, mode, gp(td.path) + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw, brow, xc,
                         utc, bnd, ubnd, par, pt);
 
+  after_rollout();  // the fused iteration issues the next sweep's register loads here
   // partials of this leaf chain
   const double qnan = __longlong_as_double(0x7ff8000000000000LL);
   double s0 = pt.nan ? qnan : pt.s0, s1 = pt.s1, s2 = pt.s2;
@@ -1188,7 +1194,7 @@ __global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forw
     return;
   }
   const Iter<T> x = make_iter(td, st, ctab, mode);
-  fwd_item<T, NXL, UP, CH, false>(sys, td, wi, st, x, mode, smem_raw, s_last, done_out);
+  fwd_item<T, NXL, UP, CH, false>(sys, td, wi, st, x, mode, smem_raw, s_last, done_out, [] {});
 }
 
 // One fused APG iteration: the forward rollout of iteration nu for a leaf
@@ -1219,12 +1225,15 @@ __global__ __launch_bounds__(kBlock, (iter_min_blocks<T, KP, NXL, FCH>())) void 
     return;
   }
   const Iter<T> xf = make_iter(td, st, ctab, kModeAPG);
-  fwd_item<T, NXL, KP, FCH, true>(sys, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out);
-  __syncthreads();  // the LDS now holds the backward layout
-  const Iter<T> xb = make_iter_at(td, st, ctab, kModeAPG, xf.it + 1);
+  // P and the B' row of the backward half are loaded while the forward half
+  // folds its partials (few registers are live there)
   T preg[KS * NT];
   RowCache<T, kNnzBt> bt;
-  bwd_setup<T, KP, NXL, BCH>(sys, smem_raw, preg, bt);
+  fwd_item<T, NXL, KP, FCH, true>(sys, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out,
+                                  [&] { bwd_load_regs<T, KP>(sys, preg, bt); });
+  __syncthreads();  // the LDS now holds the backward layout
+  const Iter<T> xb = make_iter_at(td, st, ctab, kModeAPG, xf.it + 1);
+  bwd_zero_rows<T, KP, NXL, BCH>(sys, smem_raw);
   int par = 0;
   bwd_item<T, KP, NXL, BCH, true>(sys, td, xb, kModeAPG, wi.chain, smem_raw, preg, bt, par, s_last);
 }
