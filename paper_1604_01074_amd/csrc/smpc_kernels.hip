@@ -1024,33 +1024,53 @@ constexpr int fwd_min_blocks() {
 // iteration (stop test, counters).  AG: the ancestors' dual entries this
 // chain owns are stored at device scope (the fused iteration reads them in
 // the same launch).
-template <typename T, int NXL, int UP, int CH, bool AG, typename AfterRollout>
-__device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const TreeDev<T>& td, const WorkItem wi,
-                                         G<TreeState>* st, const Iter<T>& x, int mode, unsigned char* smem_raw,
-                                         int& s_last, int32_t* __restrict__ done_out, AfterRollout after_rollout) {
+// Per-thread system rows and bounds of the thread's role in the forward
+// rollout.  They depend on the system only, so kernels load them first,
+// while the work item, tree and tree state are still on their way.
+template <typename T, int NXL>
+struct FwdSys {
+  RowCache<T, kNnzB> brow[NXL];
+  T bnd[NXL][2];
+  T ubnd[2];
+};
+
+template <typename T, int NXL>
+__device__ __forceinline__ void fwd_sys_loads(const SysDev<T>& sys, FwdSys<T, NXL>& f) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int nx = sys.nx, nu = sys.nu;
   const int j = tid - 128;
-  double* sRed = reinterpret_cast<double*>(smem_raw + lds_bytes_forward(nx, nu, sizeof(T), CH) - 32 * sizeof(double));
-
-  // per-thread system rows, bounds and carries of the thread's role
-  RowCache<T, kNnzB> brow[NXL];
-  T bnd[NXL][2];
-  T xc[NXL];
 #pragma unroll
   for (int r = 0; r < NXL; ++r) {
     const int i = lane + 64 * r;
     const bool vi = wave < 2 && i < nx;
-    load_row(brow[r], sys.b_rp, sys.b_ci, sys.b_v, i, vi);
-    bnd[r][0] = vi ? (wave == 0 ? gp(sys.xs)[i] : gp(sys.xmin)[i]) : T(0);
-    bnd[r][1] = vi ? gp(sys.xmax)[i] : T(0);
-    xc[r] = (vi && x.affine) ? gp(td.p)[i] : T(0);
+    load_row(f.brow[r], sys.b_rp, sys.b_ci, sys.b_v, i, vi);
+    f.bnd[r][0] = vi ? (wave == 0 ? gp(sys.xs)[i] : gp(sys.xmin)[i]) : T(0);
+    f.bnd[r][1] = vi ? gp(sys.xmax)[i] : T(0);
   }
-  T ubnd[2];
-  ubnd[0] = (wave >= 2 && j < nu) ? gp(sys.umin)[j] : T(0);
-  ubnd[1] = (wave >= 2 && j < nu) ? gp(sys.umax)[j] : T(0);
+  f.ubnd[0] = (wave >= 2 && j < nu) ? gp(sys.umin)[j] : T(0);
+  f.ubnd[1] = (wave >= 2 && j < nu) ? gp(sys.umax)[j] : T(0);
+}
+
+template <typename T, int NXL, int UP, int CH, bool AG, typename AfterRollout>
+__device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, NXL>& fs, const TreeDev<T>& td,
+                                         const WorkItem wi, G<TreeState>* st, const Iter<T>& x, int mode,
+                                         unsigned char* smem_raw, int& s_last, int32_t* __restrict__ done_out,
+                                         AfterRollout after_rollout) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nx = sys.nx, nu = sys.nu;
+  double* sRed = reinterpret_cast<double*>(smem_raw + lds_bytes_forward(nx, nu, sizeof(T), CH) - 32 * sizeof(double));
+
+  // the carries of the thread's role: the root's parent state
+  T xc[NXL];
+#pragma unroll
+  for (int r = 0; r < NXL; ++r) {
+    const int i = lane + 64 * r;
+    xc[r] = (wave < 2 && i < nx && x.affine) ? gp(td.p)[i] : T(0);
+  }
   T utc = T(0);
   int par = 0;
   Partials pt{0.0, 0.0, 0.0, false};
@@ -1059,8 +1079,8 @@ __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const TreeDev<T>&
   // chain itself, as one sequence
   const int p0 = gp(td.path_off)[wi.chain], p1 = gp(td.path_off)[wi.chain + 1];
   const ChainDesc ch = gp(td.chains)[wi.chain];
-  fwd_nodes<T, NXL, UP, CH, AG>(sys, td, x, mode, gp(td.path) + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw, brow, xc,
-                        utc, bnd, ubnd, par, pt);
+  fwd_nodes<T, NXL, UP, CH, AG>(sys, td, x, mode, gp(td.path) + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw,
+                                fs.brow, xc, utc, fs.bnd, fs.ubnd, par, pt);
 
   after_rollout();  // the fused iteration issues the next sweep's register loads here
   // partials of this leaf chain
@@ -1186,6 +1206,8 @@ __global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forw
   const int mode = MODE == kModeAny ? mode_arg : MODE;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_last;
+  FwdSys<T, NXL> fs;
+  fwd_sys_loads<T, NXL>(sys, fs);
   const WorkItem wi = items[blockIdx.x];
   const TreeDev<T>& td = trees[wi.tree];
   G<TreeState>* st = gp(td.st);
@@ -1194,7 +1216,7 @@ __global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forw
     return;
   }
   const Iter<T> x = make_iter(td, st, ctab, mode);
-  fwd_item<T, NXL, UP, CH, false>(sys, td, wi, st, x, mode, smem_raw, s_last, done_out, [] {});
+  fwd_item<T, NXL, UP, CH, false>(sys, fs, td, wi, st, x, mode, smem_raw, s_last, done_out, [] {});
 }
 
 // One fused APG iteration: the forward rollout of iteration nu for a leaf
@@ -1217,6 +1239,8 @@ __global__ __launch_bounds__(kBlock, (iter_min_blocks<T, KP, NXL, FCH>())) void 
   constexpr int NT = KP / 64, KS = KP / 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_last;
+  FwdSys<T, NXL> fs;
+  fwd_sys_loads<T, NXL>(sys, fs);
   const WorkItem wi = items[blockIdx.x];
   const TreeDev<T>& td = trees[wi.tree];
   G<TreeState>* st = gp(td.st);
@@ -1229,7 +1253,7 @@ __global__ __launch_bounds__(kBlock, (iter_min_blocks<T, KP, NXL, FCH>())) void 
   // folds its partials (few registers are live there)
   T preg[KS * NT];
   RowCache<T, kNnzBt> bt;
-  fwd_item<T, NXL, KP, FCH, true>(sys, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out,
+  fwd_item<T, NXL, KP, FCH, true>(sys, fs, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out,
                                   [&] { bwd_load_regs<T, KP>(sys, preg, bt); });
   __syncthreads();  // the LDS now holds the backward layout
   const Iter<T> xb = make_iter_at(td, st, ctab, kModeAPG, xf.it + 1);
