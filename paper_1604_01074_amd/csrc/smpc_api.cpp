@@ -355,7 +355,9 @@ int plan_build(smpc_ctx* ctx, const std::vector<smpc_tree*>& trees, bool need32,
   std::vector<std::pair<int, WorkItem>> lv;
   for (size_t k = 0; k < trees.size(); ++k) {
     const smpc_tree* t = trees[k];
-    for (int32_t c : t->leaves) lv.push_back({t->chains[c].len, WorkItem{(int32_t)k, c}});
+    for (int32_t c : t->leaves)
+      lv.push_back({t->chains[c].len, WorkItem{(int32_t)k, c, t->chains[c].first, t->chains[c].len, t->path_off[c],
+                                               t->path_off[c + 1] - t->path_off[c]}});
   }
   std::stable_sort(lv.begin(), lv.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
   std::vector<WorkItem> items;

@@ -45,7 +45,11 @@ struct ChainDesc {
 
 struct WorkItem {
   int32_t tree;   // slot in the launch's tree table
-  int32_t chain;  // chain id within that tree
+  int32_t chain;  // chain id within that tree (a leaf chain)
+  int32_t first;  // its first node (internal index) and length
+  int32_t len;
+  int32_t p0;     // its ancestor nodes: path[p0, p0 + plen)
+  int32_t plen;
 };
 
 // Per-tree iteration state, resident on the device.  Written by the host

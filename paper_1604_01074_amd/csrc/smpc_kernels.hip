@@ -1076,10 +1076,8 @@ __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, N
   Partials pt{0.0, 0.0, 0.0, false};
 
   // the root path (ancestor nodes of this leaf chain, root first), then the
-  // chain itself, as one sequence
-  const int p0 = gp(td.path_off)[wi.chain], p1 = gp(td.path_off)[wi.chain + 1];
-  const ChainDesc ch = gp(td.chains)[wi.chain];
-  fwd_nodes<T, NXL, UP, CH, AG>(sys, td, x, mode, gp(td.path) + p0, p1 - p0, ch.first, p1 - p0 + ch.len, smem_raw,
+  // chain itself, as one sequence (the work item carries both ranges)
+  fwd_nodes<T, NXL, UP, CH, AG>(sys, td, x, mode, gp(td.path) + wi.p0, wi.plen, wi.first, wi.plen + wi.len, smem_raw,
                                 fs.brow, xc, utc, fs.bnd, fs.ubnd, par, pt);
 
   after_rollout();  // the fused iteration issues the next sweep's register loads here
