@@ -308,7 +308,7 @@ namespace {
 // ---------------------------------------------------------------------------
 template <typename T, int KP, int NXL, int CH, bool AG>
 __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode, int chain,
-                          unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
+                          const ChainDesc ch, unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
                           const RowCache<T, kNnzBt>& bt, int& par) {
   constexpr int RS = CH + 1;  // row stride of the transposed rho (bank spread)
   constexpr int NT = KP / 64, KS = KP / 4, MT = CH / 16;
@@ -320,7 +320,6 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
   const int nx = sys.nx, nu = sys.nu, D = sys.D;
   const int j = tid - 128;
   const bool ju = wave >= 2 && j < nu;
-  const ChainDesc ch = gp(td.chains)[chain];
 
   T* sQ = reinterpret_cast<T*>(smem_raw);  // 2 x CH x XS: Q parts of waves 0, 1
   T* sRt = sQ + 2 * CH * XS;               // KP x RS: sRt[j * RS + cc]; rows nu..KP-1 zero
@@ -585,16 +584,18 @@ __device__ __forceinline__ void bwd_zero_rows(const SysDev<T>& sys, unsigned cha
 // other workgroups and is read at device scope.
 template <typename T, int KP, int NXL, int CH, bool AGP>
 __device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode,
-                                         int leaf, unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
-                                         const RowCache<T, kNnzBt>& bt, int& par, int& s_last) {
+                                         int leaf, const ChainDesc leaf_desc, unsigned char* smem_raw,
+                                         const T (&preg)[KP / 4 * (KP / 64)], const RowCache<T, kNnzBt>& bt,
+                                         int& par, int& s_last) {
   const int tid = threadIdx.x;
   int chain = leaf;
+  ChainDesc ch = leaf_desc;
   while (true) {
     if (AGP && chain != leaf)
-      bwd_chain<T, KP, NXL, CH, true>(sys, td, x, mode, chain, smem_raw, preg, bt, par);
+      bwd_chain<T, KP, NXL, CH, true>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par);
     else
-      bwd_chain<T, KP, NXL, CH, false>(sys, td, x, mode, chain, smem_raw, preg, bt, par);
-    const int parent = gp(td.chains)[chain].parent;
+      bwd_chain<T, KP, NXL, CH, false>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par);
+    const int parent = ch.parent;
     if (parent < 0) break;  // the root chain is done: the sweep is complete
     // this chain's top terms are stored: count this child done at the parent
     wait_mem();
@@ -608,6 +609,7 @@ __device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T>&
     __syncthreads();
     if (!s_last) break;  // a sibling is still running; it will sweep the parent
     chain = parent;
+    ch = gp(td.chains)[chain];
   }
 }
 
@@ -632,7 +634,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
     const G<TreeState>* st = gp(td.st);
     if (st->done) continue;
     const Iter<T> x = make_iter(td, st, ctab, mode);
-    bwd_item<T, KP, NXL, CH, false>(sys, td, x, mode, wi.chain, smem_raw, preg, bt, par, s_last);
+    bwd_item<T, KP, NXL, CH, false>(sys, td, x, mode, wi.chain, gp(td.chains)[wi.chain], smem_raw, preg, bt, par,
+                                    s_last);
   }
 }
 
@@ -1249,15 +1252,20 @@ __global__ __launch_bounds__(kBlock, (iter_min_blocks<T, KP, NXL, FCH>())) void 
   const Iter<T> xf = make_iter(td, st, ctab, kModeAPG);
   // P and the B' row of the backward half are loaded while the forward half
   // folds its partials (few registers are live there)
+  // (and the next iteration's record and this chain's descriptor)
   T preg[KS * NT];
   RowCache<T, kNnzBt> bt;
-  fwd_item<T, NXL, KP, FCH, true>(sys, fs, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out,
-                                  [&] { bwd_load_regs<T, KP>(sys, preg, bt); });
+  Iter<T> xb;
+  ChainDesc leaf_desc;
+  fwd_item<T, NXL, KP, FCH, true>(sys, fs, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out, [&] {
+    bwd_load_regs<T, KP>(sys, preg, bt);
+    xb = make_iter_at(td, st, ctab, kModeAPG, xf.it + 1);
+    leaf_desc = gp(td.chains)[wi.chain];
+  });
   __syncthreads();  // the LDS now holds the backward layout
-  const Iter<T> xb = make_iter_at(td, st, ctab, kModeAPG, xf.it + 1);
   bwd_zero_rows<T, KP, NXL, BCH>(sys, smem_raw);
   int par = 0;
-  bwd_item<T, KP, NXL, BCH, true>(sys, td, xb, kModeAPG, wi.chain, smem_raw, preg, bt, par, s_last);
+  bwd_item<T, KP, NXL, BCH, true>(sys, td, xb, kModeAPG, wi.chain, leaf_desc, smem_raw, preg, bt, par, s_last);
 }
 
 template <typename T>
