@@ -597,11 +597,13 @@ __device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T>&
       bwd_chain<T, KP, NXL, CH, false>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par);
     const int parent = ch.parent;
     if (parent < 0) break;  // the root chain is done: the sweep is complete
+    // the parent's descriptor is fetched while this chain's stores drain
+    const ChainDesc pdesc = gp(td.chains)[parent];
     // this chain's top terms are stored: count this child done at the parent
     wait_mem();
     __syncthreads();
     if (tid == 0) {
-      const int pc = gp(td.chains)[parent].child_count;
+      const int pc = pdesc.child_count;
       const int prev = __hip_atomic_fetch_add(gp(td.cnt) + parent, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       s_last = (prev == pc - 1);
       if (s_last) __hip_atomic_store(gp(td.cnt) + parent, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next iteration
@@ -609,7 +611,7 @@ __device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T>&
     __syncthreads();
     if (!s_last) break;  // a sibling is still running; it will sweep the parent
     chain = parent;
-    ch = gp(td.chains)[chain];
+    ch = pdesc;
   }
 }
 
