@@ -255,6 +255,49 @@ def test_batch_equals_alone_bitwise(ctx, lib):
         ctx.systems.remove(system)
 
 
+def test_full_batch_sampled_trees(ctx, lib):
+    """The batched workload at full size (64 trees, 259 942 nodes) in the
+    configuration the benchmark times (precond 2, tuned chunk pairs): sampled
+    trees give the bits of their own solves in float64 and in float32 with a
+    float64 polish, and the smallest and the largest match the oracle in
+    float64."""
+    _, solver = lib
+    insts = ds.batch_instances(64)
+    sizes = [i.M for i in insts]
+    print(f"[batch64] nodes={sum(sizes)} smallest={min(sizes)} largest={max(sizes)}", flush=True)
+    system = ctx.system(insts[0].sys)
+    trees = []
+    for inst in insts:
+        t = system.tree(inst.tree)
+        t.set_data(inst.d, inst.alpha2)
+        t.factor(precond=2, power_iters=100)
+        trees.append(t)
+    small, large = int(np.argmin(sizes)), int(np.argmax(sizes))
+    sample = sorted({0, small, large, len(insts) - 1})
+    ps, qs = [i.p for i in insts], [i.q for i in insts]
+    try:
+        for precision, polish, iters in ((64, 0, 40), (32, 20, 60)):
+            kw = dict(tol=0.0, max_iter=iters, check_every=10, precision=precision, polish_iters=polish)
+            print(f"[batch64] precision={precision} iterations={iters} sample={sample}", flush=True)
+            _, batch = system.solve_batch(trees, ps, qs, tune=1, **kw)
+            for k in sample:
+                alone = trees[k].solve(ps[k], qs[k], **kw)
+                assert alone["iterations"] == batch[k]["iterations"]
+                for key in ("u", "x", "y"):
+                    assert np.array_equal(alone[key], batch[k][key]), (k, key)
+            if precision == 64:
+                for k in (small, large):
+                    print(f"[batch64] oracle tree={k} M={sizes[k]}", flush=True)
+                    lam, S = trees[k].factor_info(with_scale=True)
+                    r = O.apg(O.OracleProblem.from_instance(insts[k]), lam, iters, tol=0.0, check_every=10,
+                              scale=S)
+                    assert _rel(batch[k]["u"], r.u) <= 1e-9 and _rel(batch[k]["x"], r.x) <= 1e-9
+                    assert _rel(batch[k]["y"], r.y) <= 1e-9
+    finally:
+        system.close()
+        ctx.systems.remove(system)
+
+
 def test_torch_stream_interop(ctx, lib):
     """The library runs on a torch side stream (one HIP runtime in the
     process) and gives the same bits as on its own stream."""
