@@ -343,6 +343,9 @@ void plan_free(smpc_ctx* ctx, Plan* p) {
   ctx->release(p->td64);
   ctx->release(p->td32);
   ctx->release(p->done);
+  if (p->done_pinned) (void)hipHostFree(p->done_pinned);
+  for (hipEvent_t& e : p->done_ev)
+    if (e) (void)hipEventDestroy(e);
   delete p;
 }
 
@@ -381,6 +384,9 @@ int plan_build(smpc_ctx* ctx, const std::vector<smpc_tree*>& trees, bool need32,
   if (e == hipSuccess) e = hipMemcpyAsync(p->td64.ptr, t64.data(), sizeof(TreeDev<double>) * t64.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && need32) e = hipMemcpyAsync(p->td32.ptr, t32.data(), sizeof(TreeDev<float>) * t32.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(p->done.ptr, 0, sizeof(int32_t) * trees.size(), s);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&p->done_pinned, 2 * sizeof(int32_t) * std::max<size_t>(trees.size(), 1));
+  for (hipEvent_t& ev : p->done_ev)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     plan_free(ctx, p);
@@ -515,6 +521,23 @@ int read_done(smpc_ctx* ctx, Plan* p) {
   return SMPC_OK;
 }
 
+// Stop flags through pinned slot `slot`: the copy behind the work enqueued so
+// far, and the wait for it.
+int copy_done(smpc_ctx* ctx, Plan* p, int slot) {
+  const size_t nt = p->trees.size();
+  HIP_TRY(hipMemcpyAsync(p->done_pinned + slot * nt, p->done.ptr, sizeof(int32_t) * nt, hipMemcpyDeviceToHost,
+                         ctx->stream));
+  HIP_TRY(hipEventRecord(p->done_ev[slot], ctx->stream));
+  return SMPC_OK;
+}
+
+int wait_done(Plan* p, int slot) {
+  const size_t nt = p->trees.size();
+  HIP_TRY(hipEventSynchronize(p->done_ev[slot]));
+  std::copy(p->done_pinned + slot * nt, p->done_pinned + (slot + 1) * nt, p->done_host.begin());
+  return SMPC_OK;
+}
+
 // Chunk-length autotuner: run the plan's next APG blocks with each listed
 // (backward, forward) pair in turn -- one block to instantiate its graph and
 // load its code, then two timed blocks -- and keep the pair with the
@@ -588,12 +611,26 @@ int run_until_done(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int check_every, int m
   int round = 0;
   std::fill(p->done_host.begin(), p->done_host.end(), 0);
   if (tune && !p->tuned[pix<T>()]) SMPC_TRY(tune_chunks<T>(ctx, sys, p, check_every, max_rounds, round));
-  for (; round < max_rounds; ++round) {
-    if (plan_all_done(p)) return SMPC_OK;
-    SMPC_TRY(run_block<T>(ctx, sys, p, kModeAPG, check_every));
-    SMPC_TRY(read_done(ctx, p));
-  }
   if (plan_all_done(p)) return SMPC_OK;
+  if (round >= max_rounds) return set_error(SMPC_EDEVICE, "iteration driver did not terminate");
+  // Blocks run one ahead of the host's read of the stop flags: the flags
+  // behind block k are copied to pinned memory, block k + 1 is enqueued, and
+  // only then does the host wait for the copy, so the device does not idle
+  // while the host reads them.  A block enqueued after every tree has stopped
+  // changes nothing (each kernel returns at once for a stopped tree) and is
+  // ordered before whatever the caller enqueues next.
+  int slot = 0;
+  SMPC_TRY(run_block<T>(ctx, sys, p, kModeAPG, check_every));
+  SMPC_TRY(copy_done(ctx, p, slot));
+  for (++round;; ++round) {
+    const bool more = round < max_rounds;
+    if (more) SMPC_TRY(run_block<T>(ctx, sys, p, kModeAPG, check_every));
+    SMPC_TRY(wait_done(p, slot));  // the flags behind the previous block
+    if (plan_all_done(p)) return SMPC_OK;
+    if (!more) break;
+    slot ^= 1;
+    SMPC_TRY(copy_done(ctx, p, slot));
+  }
   return set_error(SMPC_EDEVICE, "iteration driver did not terminate");
 }
 
