@@ -384,9 +384,6 @@ int plan_build(smpc_ctx* ctx, const std::vector<smpc_tree*>& trees, bool need32,
   if (e == hipSuccess) e = hipMemcpyAsync(p->td64.ptr, t64.data(), sizeof(TreeDev<double>) * t64.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && need32) e = hipMemcpyAsync(p->td32.ptr, t32.data(), sizeof(TreeDev<float>) * t32.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(p->done.ptr, 0, sizeof(int32_t) * trees.size(), s);
-  if (e == hipSuccess) e = hipHostMalloc((void**)&p->done_pinned, 2 * sizeof(int32_t) * std::max<size_t>(trees.size(), 1));
-  for (hipEvent_t& ev : p->done_ev)
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     plan_free(ctx, p);
@@ -522,7 +519,16 @@ int read_done(smpc_ctx* ctx, Plan* p) {
 }
 
 // Stop flags through pinned slot `slot`: the copy behind the work enqueued so
-// far, and the wait for it.
+// far, and the wait for it.  The two slots and their events are made on the
+// plan's first use (plan_free releases them).
+int ensure_done_slots(Plan* p) {
+  if (!p->done_pinned)
+    HIP_TRY(hipHostMalloc((void**)&p->done_pinned, 2 * sizeof(int32_t) * std::max<size_t>(p->trees.size(), 1)));
+  for (hipEvent_t& ev : p->done_ev)
+    if (!ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  return SMPC_OK;
+}
+
 int copy_done(smpc_ctx* ctx, Plan* p, int slot) {
   const size_t nt = p->trees.size();
   HIP_TRY(hipMemcpyAsync(p->done_pinned + slot * nt, p->done.ptr, sizeof(int32_t) * nt, hipMemcpyDeviceToHost,
@@ -619,6 +625,7 @@ int run_until_done(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int check_every, int m
   // while the host reads them.  A block enqueued after every tree has stopped
   // changes nothing (each kernel returns at once for a stopped tree) and is
   // ordered before whatever the caller enqueues next.
+  SMPC_TRY(ensure_done_slots(p));
   int slot = 0;
   SMPC_TRY(run_block<T>(ctx, sys, p, kModeAPG, check_every));
   SMPC_TRY(copy_done(ctx, p, slot));

@@ -161,8 +161,9 @@ struct Plan {
   int n_items = 0;  // leaf chains of all trees
   smpc::DevBuf items, td64, td32, done;
   std::vector<int32_t> done_host;
-  // two pinned host copies of the stop flags and the events behind them: the
-  // solve driver reads one block's flags while the next block runs
+  // two pinned host copies of the stop flags and the events behind them
+  // (made on the solve driver's first use): it reads one block's flags while
+  // the next block runs
   int32_t* done_pinned = nullptr;
   hipEvent_t done_ev[2] = {nullptr, nullptr};
   bool has32 = false;
