@@ -127,7 +127,7 @@ struct Chunks;
 template <>
 struct Chunks<float> {
   static constexpr int bwd[2] = {16, 32};
-  static constexpr int fwd[2] = {8, 16};
+  static constexpr int fwd[2] = {8, 4};
 };
 template <>
 struct Chunks<double> {

@@ -150,7 +150,7 @@ def test_chunk_option_errors(ctx, lib):
     inst = ds.tiny_instance()
     system, tree = solver.from_instance(ctx, inst, lambda_override=1.0)
     try:
-        for bad in (dict(chunk32=(24, 8)), dict(chunk32=(16, 4)), dict(chunk64=(16, 16)), dict(tune=2)):
+        for bad in (dict(chunk32=(24, 8)), dict(chunk32=(16, 16)), dict(chunk64=(16, 16)), dict(tune=2)):
             with pytest.raises(S.SmpcError) as ei:
                 tree.solve(inst.p, inst.q, tol=0.0, max_iter=10, **bad)
             assert ei.value.code == S.EINVAL
