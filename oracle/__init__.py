@@ -19,6 +19,11 @@ from .smpc_oracle import (
     theta_sequence,
     apg,
     primal_cost,
+    stage_cost,
+    soft_cost,
+    support_g,
+    dual_objective,
+    duality_gap,
     dual_hessian_dense,
     dual_lmax_power,
     shift_map,
@@ -37,6 +42,11 @@ __all__ = [
     "theta_sequence",
     "apg",
     "primal_cost",
+    "stage_cost",
+    "soft_cost",
+    "support_g",
+    "dual_objective",
+    "duality_gap",
     "dual_hessian_dense",
     "dual_lmax_power",
     "shift_map",

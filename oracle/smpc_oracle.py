@@ -454,8 +454,12 @@ def apg(P: OracleProblem, lam: float, iters: int, F: Factor | None = None, *, to
 # objective and step size (Sec. IV-A, IV-D)
 # ---------------------------------------------------------------------------
 
-def primal_cost(P: OracleProblem, x: np.ndarray, u: np.ndarray) -> float:
-    """``E V + V_s`` of eq. Sc-MPC at ``(x, u)`` (box indicator not added)."""
+def stage_cost(P: OracleProblem, u: np.ndarray) -> float:
+    """The smooth part of ``f`` (eq. fz): the expected economic cost plus the
+    smoothing cost, ``sum_n pi_n [W_a (a1 + a2_{s(n)})' u_n + du_n' Wu du_n]``
+    with ``du_n = u_n - u_{a(n)}`` and ``u_{a(root)} = q``.  (The indicators
+    of the dynamics and of the coupling are zero on every point this is
+    evaluated at.)"""
     cost = 0.0
     for n in range(P.M):
         a = int(P.parent[n])
@@ -463,10 +467,63 @@ def primal_cost(P: OracleProblem, x: np.ndarray, u: np.ndarray) -> float:
         du = u[n] - ua
         pi = P.prob[n]
         cost += pi * (P.W_alpha * (P.alpha1 + P.alpha2[P.stage[n]]) @ u[n] + du @ P.Wu @ du)
-    ds = np.linalg.norm(x - np.maximum(x, P.xs[None, :]), axis=1)
-    db = np.linalg.norm(x - np.clip(x, P.xmin[None, :], P.xmax[None, :]), axis=1)
-    cost += float(P.safety_weight() @ ds + P.box_weight() @ db)
     return float(cost)
+
+
+def soft_cost(P: OracleProblem, xs_part: np.ndarray, xz_part: np.ndarray) -> float:
+    """The distance terms of ``g`` (eq. gzeta): ``sum_n cS_n dist(sigma_n |
+    x >= xs) + cd_n dist(zeta_n | [xmin, xmax])`` (Euclidean distances)."""
+    ds = np.linalg.norm(xs_part - np.maximum(xs_part, P.xs[None, :]), axis=1)
+    db = np.linalg.norm(xz_part - np.clip(xz_part, P.xmin[None, :], P.xmax[None, :]), axis=1)
+    return float(P.safety_weight() @ ds + P.box_weight() @ db)
+
+
+def primal_cost(P: OracleProblem, x: np.ndarray, u: np.ndarray) -> float:
+    """``E V + V_s`` of eq. Sc-MPC at ``(x, u)`` (box indicator not added)."""
+    return stage_cost(P, u) + soft_cost(P, x, x)
+
+
+def support_g(P: OracleProblem, y: np.ndarray) -> tuple[float, float]:
+    """``g*(y)`` (App. C's sets, conjugates by definition): the conjugate of
+    ``c dist(. | C)`` is the support function of ``C`` plus the indicator of
+    the ball of radius ``c``; the conjugate of the indicator of the input box
+    is its support function.  Returns ``(value, violation)``: the value of the
+    support-function terms and the largest violation of the domain (the sign
+    condition ``sigma~ <= 0`` of the half-space ``x >= xs`` and the two ball
+    radii), which is ``<= 0`` exactly when ``y`` lies in ``dom g*``."""
+    nx = P.nx
+    ys, yz, yp = y[:, :nx], y[:, nx:2 * nx], y[:, 2 * nx:]
+    val = float(np.sum(ys * P.xs) + np.sum(np.maximum(yz * P.xmax, yz * P.xmin))
+                + np.sum(np.maximum(yp * P.umax, yp * P.umin)))
+    viol = max(float(np.max(ys)),
+               float(np.max(np.linalg.norm(ys, axis=1) - P.safety_weight())),
+               float(np.max(np.linalg.norm(yz, axis=1) - P.box_weight())))
+    return val, viol
+
+
+def dual_objective(P: OracleProblem, F: Factor, y: np.ndarray) -> tuple[float, float]:
+    """Dual objective of eq. optim:prob, ``D(y) = f*(-H'y) + g*(y)``, for an
+    unscaled dual ``y``.  ``f*(-H'y) = -(f(z_y) + <y, H z_y>)`` with ``z_y``
+    the minimiser of ``<z, H'y> + f(z)`` (Alg. 1, the conjugate subgradient
+    theorem used in Sec. IV-A).  Returns ``(D(y), domain violation)`` as in
+    ``support_g``; ``D(y) >= -V*`` for every ``y`` in the domain (weak
+    duality) with equality at a dual optimum (strong duality, Sec. IV-A)."""
+    x, u = solve_step(P, F, y)
+    fconj = -(stage_cost(P, u) + float(np.sum(y * hz(x, u))))
+    sval, viol = support_g(P, y)
+    return fconj + sval, viol
+
+
+def duality_gap(P: OracleProblem, F: Factor, x: np.ndarray, u: np.ndarray, t: np.ndarray,
+                y: np.ndarray) -> float:
+    """A-posteriori duality gap of Sec. IV-E for a primal pair ``(z, t)`` and
+    a dual ``y`` (all unscaled): ``f(z) + g(t) + D(y)``.  ``t`` must satisfy
+    the input box (the prox output always does); the soft terms of ``g`` are
+    the distances of its state blocks.  For ``H z = t`` and ``y`` in the
+    domain of ``g*`` this is ``>= 0`` (weak duality), and it tends to 0 with
+    the APG's ``(z^nu, t^nu, y^{nu+1})``."""
+    nx = P.nx
+    return stage_cost(P, u) + soft_cost(P, t[:, :nx], t[:, nx:2 * nx]) + dual_objective(P, F, y)[0]
 
 
 def _dual_hessian_apply(P: OracleProblem, F: Factor, w: np.ndarray, svec: np.ndarray) -> np.ndarray:
