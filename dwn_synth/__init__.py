@@ -14,6 +14,7 @@ from .instances import (
     Instance,
     tiny_instance,
     barcelona_instance,
+    table1_instance,
     batch_instances,
     random_small_instance,
     barcelona_demands,
@@ -32,6 +33,7 @@ __all__ = [
     "Instance",
     "tiny_instance",
     "barcelona_instance",
+    "table1_instance",
     "batch_instances",
     "random_small_instance",
     "barcelona_demands",

@@ -28,7 +28,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .systems import barcelona_shaped_system, random_dense_system, tiny_tank_system
-from .trees import uniform_tree
+from .trees import table1_tree, uniform_tree
 
 
 @dataclass
@@ -121,6 +121,19 @@ def barcelona_instance(seed: int = 1, N: int = 24, branching=(7, 7, 7), sys: dic
 
 BATCH_SHAPES = {16: [4, 4], 64: [4, 4, 4], 125: [5, 5, 5], 343: [7, 7, 7], 512: [8, 8, 8]}
 BATCH_HORIZONS = (12, 18, 24)
+
+
+def table1_instance(name: str, seed: int = 1, sys: dict | None = None) -> Instance:
+    """A Table 1 controller (Sec. V-B: its branching and scenario count, N =
+    24) on the Barcelona-shaped system, with demands, pumping cost and initial
+    state drawn as in ``barcelona_instance``."""
+    if sys is None:
+        sys = barcelona_shaped_system(seed)
+    tree = table1_tree(name)
+    rng = np.random.default_rng([seed, 2])
+    d, uf = barcelona_demands(sys, tree, rng)
+    return Instance(f"table1-{name}", sys, tree, d, pumping_cost(sys, int(tree["N"])), 0.6 * sys["xmax"],
+                    0.3 * sys["umax"], extra={"uf": uf})
 
 
 def batch_instances(n_trees: int = 64, first_seed: int = 100, system_seed: int = 1) -> list[Instance]:

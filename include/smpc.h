@@ -55,7 +55,8 @@ enum {
   SMPC_EDEVICE = -7,        /* HIP runtime error                                   */
   SMPC_ENOTFACTORED = -8,   /* smpc_factor / smpc_tree_set_data not called yet     */
   SMPC_EDIVERGED = -9,      /* residual became non-finite or exploded              */
-  SMPC_ENAN = -10           /* NaN or Inf in an input                              */
+  SMPC_ENAN = -10,          /* NaN or Inf in an input                              */
+  SMPC_ECANCELED = -11      /* smpc_server_cancel: the request was withdrawn        */
 };
 
 typedef struct smpc_ctx smpc_ctx;
@@ -97,7 +98,8 @@ typedef struct {
 /* Copies the system, checks it (SMPC_ENAN, SMPC_EDIM, SMPC_EINVAL for
  * umin > umax or xmin > xmax, SMPC_ENOTSPD for Wu, SMPC_ERANK for E) and runs
  * the tree-independent part of the factor step (App. A / App. B) in float64
- * on the host.  Supported: 1 <= nx <= 128, 1 <= nu <= 128, 0 <= ne < nu.   */
+ * on the host.  Supported: 1 <= nx <= 128, 1 <= nu <= 128, 0 <= nd <= 4096,
+ * 0 <= ne < nu.                                                             */
 int smpc_sys_create(smpc_ctx* ctx, const smpc_sys_desc* desc, smpc_sys** out);
 int smpc_sys_destroy(smpc_sys* sys);   /* SMPC_EINVAL while trees still use it */
 
@@ -112,10 +114,22 @@ int smpc_tree_create(smpc_sys* sys, int N, int M, const int32_t* stage,
                      const int32_t* parent, const double* prob, smpc_tree** out);
 int smpc_tree_destroy(smpc_tree* tree);
 
-/* Cost update of App. A for new node demands d (M*nd, caller's node order)
- * and pumping costs alpha2 (N*nu; NULL = zero).  Computes uhat_n, e_n and the
- * linear cost terms in float64 on the host and uploads them.                 */
+/* Cost update of App. A (Alg. 2, step 2) for new node demands d (M*nd,
+ * caller's node order; NULL = zero when nd = 0) and pumping costs alpha2
+ * (N*nu; NULL = zero).  d and alpha2 are copied to the device, where float64
+ * kernels compute per node the particular input uhat_n (minimum-norm
+ * solution of E u + Ed d_n = 0), e_n = B uhat_n + Gd d_n and the linear cost
+ * of the input
+ *   beta_n = pi_n W_alpha (alpha1 + alpha2_{s(n)})
+ *            + 2 Wu (pibar_n uhat_n - pi_n uhat_{a(n)} - sum_c pi_c uhat_c),
+ *   pibar_n = pi_n + sum over the children c of pi_c
+ * (App. A writes its v-space form L' beta_n); the root's term in the previous
+ * input q is added by each solve.  Errors: SMPC_ENAN, SMPC_EDEVICE.         */
 int smpc_tree_set_data(smpc_tree* tree, const double* d, const double* alpha2);
+/* The node data the device holds, in the caller's node order (any pointer
+ * may be NULL): uhat (M*nu), e (M*nx), beta (M*nu; the root row includes the
+ * q term of the last solve, or none before the first).                      */
+int smpc_tree_get_data(smpc_tree* tree, double* uhat, double* e, double* beta);
 
 /* Step size and dual scaling (Sec. IV-D).
  * precond: 0 -> no scaling; 1 -> one scalar per (node, dual block), the
@@ -191,6 +205,7 @@ typedef struct {
   int chunk32[2];
   int chunk64[2];
   int unfused;
+  int gap;  /* 1: fill smpc_result.cost and .gap (smpc_tree_objective)   */
 } smpc_solve_opts;
 
 /* Chunk lengths built into the library for `precision` (32 or 64) and
@@ -201,7 +216,9 @@ int smpc_chunk_lengths(int precision, int which, int* out, int cap, int* n);
 /* Caller-allocated outputs; any pointer may be NULL.  u0: nu, x: M*nx,
  * u: M*nu (last primal iterate z^nu), y: M*(2nx+nu) (y^{nu+1}).
  * iterations counts all iterations, fp32_iterations the float32 ones.
- * status: SMPC_OK (stop test passed), SMPC_MAX_ITER or SMPC_EDIVERGED.      */
+ * status: SMPC_OK (stop test passed), SMPC_MAX_ITER or SMPC_EDIVERGED.
+ * cost and gap: with opts.gap = 1, the primal cost of z^nu and the duality
+ * gap of smpc_tree_objective; 0 otherwise.                                  */
 typedef struct {
   double* u0;
   double* x;
@@ -216,6 +233,8 @@ typedef struct {
   double run_ms;    /* server requests: admission -> result; 0 otherwise  */
   int chunk32[2];   /* {backward, forward} chunk lengths the float32 / float64 */
   int chunk64[2];   /* iterations ended with; {0, 0} for a precision not run  */
+  double cost;
+  double gap;
 } smpc_result;
 
 /* Solve one tree from initial state p (nx) and previous input q (nu).
@@ -247,6 +266,36 @@ int smpc_solve_batch(smpc_tree* const* trees, int n, const double* const* p,
  * discard the resident dual) or for a realized index out of range.         */
 int smpc_shift_warm_start(smpc_tree* tree, int realized);
 
+/* ------------------------------------------------------------------ objective
+ * Objectives of eq. optim:prob and the a-posteriori duality gap of
+ * Sec. IV-E at the iterates the tree's last solve left on the device: the
+ * last primal iterate z^nu, the prox output t^nu (recovered from the dual
+ * update) and the dual y^{nu+1} (unscaled).  In float64:
+ *   cost   = V(z^nu): the objective of eq. Sc-MPC at z^nu (soft terms at the
+ *            states x_n themselves, i.e. t = Hz)
+ *   primal = f(z^nu) + g(t^nu)
+ *   dual   = D(y) = f*(-H'y) + g*(y), f*(-H'y) = -(f(z_y) + <y, H z_y>) with
+ *            z_y the solve step at y (one extra solve step), g* the support
+ *            functions of the sets of g
+ *   gap    = primal + dual (>= 0 for y in dom g* by weak duality, -> 0 at
+ *            the optimum by strong duality, Sec. IV-A)
+ *   dual_violation = the largest violation of dom g* (y_sigma <= 0 and the
+ *            norm balls of radius cS_n and cd); <= 0 means y lies in it.
+ * The extra solve step overwrites the tree's primal iterate and the dual slot
+ * of y^{nu-1} (the resident dual for warm starts is kept); the values are
+ * cached, so later calls return the same numbers until the next solve.
+ * Errors: SMPC_EINVAL when the tree has no finished solve (or smpc_factor /
+ * smpc_solve_step ran since).  Device scratch: allocated by the library on
+ * first use (see smpc_tree_objective_noalloc).                              */
+typedef struct {
+  double cost;
+  double primal;
+  double dual;
+  double gap;
+  double dual_violation;
+} smpc_objective;
+int smpc_tree_objective(smpc_tree* tree, smpc_objective* out);
+
 /* ------------------------------------------------------------------ serving
  * Continuous batching of closed-loop MPC steps (the loop of Alg. 2 for many
  * controllers).  A server owns a worker thread that drives the context's
@@ -257,10 +306,15 @@ int smpc_shift_warm_start(smpc_tree* tree, int realized);
  * soon as it stops, so short requests do not wait for long ones.  A result
  * equals that of smpc_solve on the same tree and inputs bit for bit.
  * Admission: at most max_active trees iterate at once (0: no limit); a tree
- * runs one request at a time, in submission order; a request whose float32
- * buffers do not fit the context's HBM budget waits for another request to
- * finish.  While a server exists, its system and trees are used only
- * through the server calls.                                                 */
+ * runs one request at a time, in submission order.  A request whose tree
+ * needs float32 buffers is admitted only when they fit both the context's
+ * HBM budget and the device's free memory (hipMemGetInfo, less a 1/16
+ * reserve); otherwise the server first releases the float32 buffers of idle
+ * trees (least recently finished first; a tree whose resident dual is
+ * float32 keeps them), and if that is not enough the request waits, ahead
+ * of later requests and in submission order, until a running request
+ * finishes.  With nothing running it fails with SMPC_ENOMEM.  While a server
+ * exists, its system and trees are used only through the server calls.     */
 typedef struct smpc_server smpc_server;
 typedef struct {
   smpc_solve_opts solve;  /* tol, max_iter, check_every, precision, polish_iters,
@@ -281,6 +335,11 @@ int smpc_server_submit(smpc_server* srv, smpc_tree* tree, const double* d, const
  * it is not done, else its status with res filled (u0 copied when res->u0 is
  * set; x, u, y must be NULL) and the ticket released.                      */
 int smpc_server_poll(smpc_server* srv, uint64_t ticket, smpc_result* res, int wait_ms);
+/* Withdraws a request: a queued one never starts, a running one stops at
+ * the end of its current iteration block.  Its poll then returns
+ * SMPC_ECANCELED (no outputs).  A request that has already finished keeps
+ * its result.  SMPC_EINVAL for an unknown ticket.                          */
+int smpc_server_cancel(smpc_server* srv, uint64_t ticket);
 /* Finishes the queued and running requests, then stops the worker.         */
 int smpc_server_destroy(smpc_server* srv);
 

@@ -44,7 +44,8 @@ def build(verbose: bool = False) -> str:
     try:
         jobs = []
         for src, defs in (("smpc_kernels.hip", ["-DSMPC_KERNEL_PART=1"]), ("smpc_kernels.hip", ["-DSMPC_KERNEL_PART=2"]),
-                          ("smpc_setup.cpp", []), ("smpc_api.cpp", []), ("smpc_server.cpp", [])):
+                          ("smpc_data.hip", []), ("smpc_setup.cpp", []), ("smpc_api.cpp", []),
+                          ("smpc_server.cpp", [])):
             obj = os.path.join(tmpdir, f"{os.path.splitext(src)[0]}{defs[0][-1] if defs else ''}.o")
             cmd = [HIPCC, *FLAGS, *defs, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:

@@ -90,6 +90,7 @@ int smpc_ctx::ensure_ctab(int n) {
   HIP_TRY(hipMalloc(&ctab, sizeof(double) * len));
   used += sizeof(double) * len;
   HIP_TRY(hipMemcpy(ctab, h.data(), sizeof(double) * len, hipMemcpyHostToDevice));
+  ctab_host = h;
   ctab_len = len;
   ++ctab_gen;
   return SMPC_OK;
@@ -307,14 +308,14 @@ void tree_free(smpc_ctx* ctx, TreeBuffers<T>& b) {
   b.allocated = false;
 }
 
-// Upload the cost-update vectors and the scaling of one precision.
-template <typename T>
-int tree_upload_data(smpc_tree* t) {
-  TreeBuffers<T>& b = treebuf<T>(t);
+// The float32 copies of the node data from the float64 device buffers (the
+// device cost update writes both precisions once the float32 buffers exist).
+int tree_narrow_data(smpc_tree* t) {
   smpc_ctx* ctx = t->sys->ctx;
-  SMPC_TRY(upload<T>(ctx, b.beta, t->beta0.data(), t->beta0.size()));
-  SMPC_TRY(upload<T>(ctx, b.uhat, t->uhat.data(), t->uhat.size()));
-  SMPC_TRY(upload<T>(ctx, b.e, t->e.data(), t->e.size()));
+  const size_t M = t->M, nx = t->sys->nx, nu = t->sys->nu;
+  HIP_TRY(launch_narrow((const double*)t->b64.beta.ptr, (float*)t->b32.beta.ptr, M * nu, ctx->stream));
+  HIP_TRY(launch_narrow((const double*)t->b64.uhat.ptr, (float*)t->b32.uhat.ptr, M * nu, ctx->stream));
+  HIP_TRY(launch_narrow((const double*)t->b64.e.ptr, (float*)t->b32.e.ptr, M * nx, ctx->stream));
   return SMPC_OK;
 }
 
@@ -653,21 +654,15 @@ int write_state(smpc_tree* t, const TreeState& h) {
   return SMPC_OK;
 }
 
-// Per-solve inputs: root parent state p and the root's linear term (depends on q).
+// Per-solve input of one precision: the root parent state p.
 template <typename T>
-int upload_root(smpc_tree* t, const double* p, const double* q) {
+int upload_root(smpc_tree* t, const double* p) {
   TreeBuffers<T>& b = treebuf<T>(t);
   smpc_ctx* ctx = t->sys->ctx;
-  const int nx = t->sys->nx, nu = t->sys->nu;
+  const int nx = t->sys->nx;
   std::vector<T> hp(nx);
   for (int i = 0; i < nx; ++i) hp[i] = (T)p[i];
-  std::vector<double> br;
-  root_beta(t, q, br);
-  std::vector<T> hb(nu);
-  for (int i = 0; i < nu; ++i) hb[i] = (T)br[i];
-  const size_t r = (size_t)t->iperm[0];
   HIP_TRY(hipMemcpyAsync(b.p.ptr, hp.data(), sizeof(T) * nx, hipMemcpyHostToDevice, ctx->stream));
-  HIP_TRY(hipMemcpyAsync((T*)b.beta.ptr + r * nu, hb.data(), sizeof(T) * nu, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return SMPC_OK;
 }
@@ -842,8 +837,9 @@ SolvePhases phases(const smpc_solve_opts* o) {
 int tree_begin(smpc_tree* t, const double* p, const double* q, const smpc_solve_opts* o, const double* y0,
                const double* yp0) {
   const SolvePhases ph = phases(o);
-  SMPC_TRY(upload_root<double>(t, p, q));
-  if (ph.run32) SMPC_TRY(upload_root<float>(t, p, q));
+  SMPC_TRY(upload_root<double>(t, p));
+  if (ph.run32) SMPC_TRY(upload_root<float>(t, p));
+  SMPC_TRY(upload_q(t, q));
   if (o->warm_start == 1) {
     if (ph.run32) SMPC_TRY(start_from_resident<float>(t));
     else SMPC_TRY(start_from_resident<double>(t));
@@ -889,6 +885,7 @@ int tree_result(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int stat
   // the final dual y^{nu+1} stays resident for a shifted warm start
   t->res_slot = h.iters_done % 3;
   t->res_prec = ph.run64 ? 64 : 32;
+  t->obj_valid = false;
   if (!r) return SMPC_OK;
   r->iterations = h.iters_done;
   r->fp32_iterations = ph.run32 ? fp32_iters : 0;
@@ -953,6 +950,176 @@ void result_chunks(const int (&chunk)[2][2], const smpc_solve_opts* o, smpc_resu
 }
 
 // Solve a set of trees (one plan) with the given options.
+// ---------------------------------------------------------------- device cost update and objectives
+
+// The float64 system matrices of the cost update and of the objectives.
+int cost_sys_upload(smpc_sys* s) {
+  smpc_ctx* ctx = s->ctx;
+  SMPC_TRY(upload<double>(ctx, s->c_Mu, s->Mu.data(), s->Mu.size()));
+  SMPC_TRY(upload<double>(ctx, s->c_Wu, s->Wu.data(), s->Wu.size()));
+  SMPC_TRY(upload<double>(ctx, s->c_Gd, s->Gd.data(), s->Gd.size()));
+  SMPC_TRY(upload<double>(ctx, s->c_alpha1, s->alpha1.data(), s->alpha1.size()));
+  CostSysDev& v = s->cview;
+  const SysDev<double>& d = s->d64.view;
+  v.nx = s->nx;
+  v.nu = s->nu;
+  v.nd = s->nd;
+  v.safety_by_prob = s->safety_by_prob;
+  v.Mu = (const double*)s->c_Mu.ptr;
+  v.Wu = (const double*)s->c_Wu.ptr;
+  v.Gd = (const double*)s->c_Gd.ptr;
+  v.b_rp = d.b_rp;
+  v.b_ci = d.b_ci;
+  v.b_v = d.b_v;
+  v.alpha1 = (const double*)s->c_alpha1.ptr;
+  v.umin = d.umin;
+  v.umax = d.umax;
+  v.xmin = d.xmin;
+  v.xmax = d.xmax;
+  v.xs = d.xs;
+  v.W_alpha = s->W_alpha;
+  v.W_x = s->W_x;
+  v.gamma_d = s->gamma_d;
+  return SMPC_OK;
+}
+
+// Node structure of the device cost update, internal order.
+int cost_tree_upload(smpc_tree* t) {
+  smpc_ctx* ctx = t->sys->ctx;
+  const int M = t->M;
+  std::vector<int32_t> st(M), par(M), crp(M + 1, 0), cci(M > 1 ? M - 1 : 1, 0);
+  for (int in = 0; in < M; ++in) {
+    const int n = t->perm[in];
+    st[in] = t->stage[n];
+    par[in] = t->parent[n] < 0 ? -1 : t->iperm[t->parent[n]];
+  }
+  for (int in = 0; in < M; ++in)
+    if (par[in] >= 0) crp[par[in] + 1]++;
+  for (int in = 0; in < M; ++in) crp[in + 1] += crp[in];
+  std::vector<int32_t> fill(crp.begin(), crp.end() - 1);
+  for (int in = 0; in < M; ++in)
+    if (par[in] >= 0) cci[fill[par[in]]++] = in;
+  SMPC_TRY(upload_i32(ctx, t->n_stage, st));
+  SMPC_TRY(upload_i32(ctx, t->n_parent, par));
+  SMPC_TRY(upload_i32(ctx, t->n_crp, crp));
+  SMPC_TRY(upload_i32(ctx, t->n_cci, cci));
+  SMPC_TRY(upload_i32(ctx, t->n_perm, t->perm));
+  const smpc_sys* s = t->sys;
+  SMPC_TRY(ctx->alloc(t->d_dev, sizeof(double) * (size_t)M * std::max(s->nd, 1)));
+  SMPC_TRY(ctx->alloc(t->a2_dev, sizeof(double) * (size_t)t->N * s->nu));
+  SMPC_TRY(ctx->alloc(t->q_dev, sizeof(double) * s->nu));
+  SMPC_TRY(ctx->alloc(t->broot0, sizeof(double) * s->nu));
+  HIP_TRY(hipMemsetAsync(t->q_dev.ptr, 0, sizeof(double) * s->nu, ctx->stream));
+  HIP_TRY(hipMemsetAsync(t->broot0.ptr, 0, sizeof(double) * s->nu, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return SMPC_OK;
+}
+
+CostTreeDev cost_tree_view(smpc_tree* t) {
+  CostTreeDev v{};
+  v.M = t->M;
+  v.N = t->N;
+  v.root = t->iperm[0];
+  v.stage = (const int32_t*)t->n_stage.ptr;
+  v.parent = (const int32_t*)t->n_parent.ptr;
+  v.child_rp = (const int32_t*)t->n_crp.ptr;
+  v.child_ci = (const int32_t*)t->n_cci.ptr;
+  v.perm = (const int32_t*)t->n_perm.ptr;
+  v.pi = (const double*)t->b64.pi.ptr;
+  v.d = (const double*)t->d_dev.ptr;
+  v.alpha2 = (const double*)t->a2_dev.ptr;
+  v.q = (const double*)t->q_dev.ptr;
+  v.uhat = (double*)t->b64.uhat.ptr;
+  v.e = (double*)t->b64.e.ptr;
+  v.beta = (double*)t->b64.beta.ptr;
+  v.beta_root0 = (double*)t->broot0.ptr;
+  if (t->b32.allocated) {
+    v.uhat32 = (float*)t->b32.uhat.ptr;
+    v.e32 = (float*)t->b32.e.ptr;
+    v.beta32 = (float*)t->b32.beta.ptr;
+  }
+  return v;
+}
+
+// The previous input q of a solve and the root's linear term it enters
+// (both precisions).
+int upload_q(smpc_tree* t, const double* q) {
+  smpc_ctx* ctx = t->sys->ctx;
+  HIP_TRY(hipMemcpyAsync(t->q_dev.ptr, q, sizeof(double) * t->sys->nu, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(launch_root_beta(t->sys->cview, cost_tree_view(t), ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return SMPC_OK;
+}
+
+int ensure_obj_scratch(smpc_tree* t) {
+  smpc_ctx* ctx = t->sys->ctx;
+  if (!t->obj_part.ptr) SMPC_TRY(ctx->alloc(t->obj_part, sizeof(double) * kObjSlots * kObjMaxBlocks));
+  if (!t->obj_out.ptr) SMPC_TRY(ctx->alloc(t->obj_out, sizeof(double) * kObjSlots));
+  return SMPC_OK;
+}
+
+// Objectives at the iterates of the tree's last solve (smpc_tree_objective),
+// with the partial sums in `part` (kObjSlots * kObjMaxBlocks doubles) and the
+// reduced values in `out_dev` (kObjSlots doubles).
+int tree_objective(smpc_tree* t, double* part, double* out_dev, smpc_objective* out) {
+  if (t->res_slot < 0)
+    return set_error(SMPC_EINVAL, "no finished solve on the device (smpc_factor or smpc_solve_step ran since)");
+  if (t->obj_valid) {
+    *out = t->obj_cache;
+    return SMPC_OK;
+  }
+  smpc_sys* s = t->sys;
+  smpc_ctx* ctx = s->ctx;
+  const int M = t->M, nx = s->nx, nu = s->nu, D = 2 * nx + nu;
+  TreeState h;
+  SMPC_TRY(read_state(t, &h));
+  const int it_done = h.iters_done;
+  if (it_done < 1 || it_done % 3 != t->res_slot || it_done > ctx->ctab_len)
+    return set_error(SMPC_EINVAL, "the tree's iteration state does not match its resident solve");
+  if (!t->plan) SMPC_TRY(ensure_single_plan(t, false));
+  TreeBuffers<double>& b = t->b64;
+  if (t->res_prec == 32) {
+    // a solve that ended in float32: its iterates, widened (exactly)
+    for (int k = 0; k < 3; ++k)
+      HIP_TRY(launch_widen<float>((const float*)t->b32.y[k].ptr, (double*)b.y[k].ptr, (size_t)M * D, ctx->stream));
+    HIP_TRY(launch_widen<float>((const float*)t->b32.z.ptr, (double*)b.z.ptr, (size_t)M * (nx + nu), ctx->stream));
+  }
+  const int sl = t->res_slot;
+  ObjDev o{};
+  o.z = (const double*)b.z.ptr;
+  o.yn = (const double*)b.y[sl].ptr;
+  o.yc = (const double*)b.y[(sl + 2) % 3].ptr;
+  o.yp = (const double*)b.y[(sl + 1) % 3].ptr;
+  o.scale = (const double*)b.scale.ptr;
+  o.c = ctx->ctab_host[it_done - 1];
+  o.lam = t->lambda;
+  const int blocks = std::min(M, kObjMaxBlocks);
+  const CostTreeDev tv = cost_tree_view(t);
+  HIP_TRY(launch_objective(s->cview, tv, o, false, part, blocks, out_dev, ctx->stream));
+  // the solve step at the unscaled dual y = S y^{nu+1}, placed in the slot of
+  // y^{nu-1}, which the solve-step mode reads at iteration it_done + 1
+  HIP_TRY(launch_scale_dual((const double*)b.y[sl].ptr, (double*)b.y[(sl + 1) % 3].ptr, o.scale, M, nx, nu,
+                            ctx->stream));
+  TreeState hs = h;
+  hs.iter = it_done + 1;
+  hs.done = 0;
+  SMPC_TRY(write_state(t, hs));
+  SMPC_TRY(enqueue_iteration<double>(ctx, s, t->plan, kModeSolve));
+  HIP_TRY(launch_objective(s->cview, tv, o, true, part, blocks, out_dev, ctx->stream));
+  double r[kObjSlots];
+  HIP_TRY(hipMemcpyAsync(r, out_dev, sizeof(r), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  SMPC_TRY(write_state(t, h));
+  out->cost = r[0] + r[2];
+  out->primal = r[0] + r[1];
+  out->dual = -(r[3] + r[4]) + r[5];
+  out->gap = out->primal + out->dual;
+  out->dual_violation = r[6];
+  t->obj_cache = *out;
+  t->obj_valid = true;
+  return SMPC_OK;
+}
+
 int solve_plan(Plan* plan, const double* const* p, const double* const* q, const smpc_solve_opts* o,
                smpc_result* res) {
   smpc_sys* sys = plan->trees[0]->sys;
@@ -992,6 +1159,15 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
     SMPC_TRY(tree_result(plan->trees[k], o, fp32_iters[k], status32[k], res ? &res[k] : nullptr));
     if (res) result_chunks(plan->chunk, o, &res[k]);
   }
+  if (o->gap && res)
+    for (int k = 0; k < n; ++k) {
+      smpc_tree* t = plan->trees[k];
+      SMPC_TRY(ensure_obj_scratch(t));
+      smpc_objective ob{};
+      SMPC_TRY(tree_objective(t, (double*)t->obj_part.ptr, (double*)t->obj_out.ptr, &ob));
+      res[k].cost = ob.cost;
+      res[k].gap = ob.gap;
+    }
   return SMPC_OK;
 }
 
@@ -1019,11 +1195,43 @@ int ensure_single_plan(smpc_tree* t, bool need32) {
   return plan_build(ctx, {t}, need32, &t->plan);
 }
 
+size_t tree32_bytes(const smpc_tree* t) {
+  const size_t M = t->M, nx = t->sys->nx, nu = t->sys->nu, D = 2 * nx + nu, C = t->chains.size();
+  return sizeof(float) * (3 * M * D + 3 * M * nu + M * nx + M + 3 * M + nx + M * (nx + nu) + C * (nx + nu));
+}
+
+size_t sys32_bytes(const smpc_sys* s) {
+  const size_t kp = p_stride(s->nu), nx = s->nx, nu = s->nu;
+  const size_t nnz = s->Bc.v.size() + s->Btc.v.size() + s->Ac.v.size() + s->Atc.v.size();
+  return sizeof(float) * (kp * kp + nnz + 2 * nu + 3 * nx) + sizeof(int32_t) * (nnz + 2 * (nx + 1) + 2 * (nu + 1));
+}
+
+int tree_release32(smpc_tree* t) {
+  smpc_ctx* ctx = t->sys->ctx;
+  if (!t->b32.allocated) return SMPC_OK;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (t->plan && t->plan->has32) {
+    plan_free(ctx, t->plan);
+    t->plan = nullptr;
+  }
+  if (ctx->batch_plan && ctx->batch_plan->has32 &&
+      std::find(ctx->batch_plan->trees.begin(), ctx->batch_plan->trees.end(), t) != ctx->batch_plan->trees.end()) {
+    plan_free(ctx, ctx->batch_plan);
+    ctx->batch_plan = nullptr;
+  }
+  tree_free(ctx, t->b32);
+  if (t->res_prec == 32) {
+    t->res_slot = -1;
+    t->shift_ready = false;
+  }
+  return SMPC_OK;
+}
+
 int prepare32(smpc_tree* t) {
   SMPC_TRY(ensure_sys32(t->sys));
   if (!t->b32.allocated) {
     SMPC_TRY(tree_alloc<float>(t));
-    if (t->has_data) SMPC_TRY(tree_upload_data<float>(t));
+    if (t->has_data) SMPC_TRY(tree_narrow_data(t));
     SMPC_TRY(tree_upload_scale<float>(t));
     SMPC_TRY(tree_alloc<float>(t));
     if (t->plan) {
@@ -1116,6 +1324,7 @@ int smpc_sys_create(smpc_ctx* ctx, const smpc_sys_desc* d, smpc_sys** out) {
   if (nx < 1 || nu < 1 || nd < 0 || ne < 0) return set_error(SMPC_EDIM, "dimensions must be positive");
   if (nu > 128) return set_error(SMPC_EDIM, "nu = %d exceeds the supported 128", nu);
   if (nx > 128) return set_error(SMPC_EDIM, "nx = %d exceeds the supported 128", nx);
+  if (nd > 4096) return set_error(SMPC_EDIM, "nd = %d exceeds the supported 4096", nd);
   if (ne >= nu) return set_error(SMPC_EDIM, "ne = %d must be < nu = %d", ne, nu);
   if (!d->A || !d->B || (nd > 0 && !d->Gd) || !d->umin || !d->umax || !d->xmin || !d->xmax || !d->xs ||
       !d->alpha1 || !d->Wu)
@@ -1170,8 +1379,11 @@ int smpc_sys_create(smpc_ctx* ctx, const smpc_sys_desc* d, smpc_sys** out) {
     return rc;
   }
   rc = sys_upload<double>(s, s->d64);
+  if (rc >= 0) rc = cost_sys_upload(s);
   if (rc < 0) {
     sys_free(ctx, s->d64);
+    DevBuf* cb[] = {&s->c_Mu, &s->c_Wu, &s->c_Gd, &s->c_alpha1};
+    for (DevBuf* b : cb) ctx->release(*b);
     delete s;
     return rc;
   }
@@ -1191,6 +1403,8 @@ int smpc_sys_destroy(smpc_sys* s) {
   }
   sys_free(ctx, s->d64);
   sys_free(ctx, s->d32);
+  DevBuf* cb[] = {&s->c_Mu, &s->c_Wu, &s->c_Gd, &s->c_alpha1};
+  for (DevBuf* b : cb) ctx->release(*b);
   ctx->n_sys--;
   delete s;
   return SMPC_OK;
@@ -1325,9 +1539,12 @@ int smpc_tree_create(smpc_sys* sys, int N, int M, const int32_t* stage, const in
     if (e != hipSuccess) rc = set_error(SMPC_EDEVICE, "tree upload failed: %s", hipGetErrorString(e));
   }
   if (rc >= 0) rc = tree_alloc<double>(t);
+  if (rc >= 0) rc = cost_tree_upload(t);
   if (rc < 0) {
     tree_free(ctx, t->b64);
-    DevBuf* extra[] = {&t->cstat, &t->st, &t->chains_dev, &t->cnt, &t->leaves_dev, &t->path_off_dev, &t->path_dev};
+    DevBuf* extra[] = {&t->cstat,  &t->st,       &t->chains_dev, &t->cnt,   &t->leaves_dev, &t->path_off_dev,
+                       &t->path_dev, &t->n_stage, &t->n_parent,  &t->n_crp, &t->n_cci,      &t->n_perm,
+                       &t->d_dev,  &t->a2_dev,   &t->q_dev,      &t->broot0};
     for (DevBuf* b : extra) ctx->release(*b);
     delete t;
     return rc;
@@ -1348,8 +1565,10 @@ int smpc_tree_destroy(smpc_tree* t) {
   if (t->plan) plan_free(ctx, t->plan);
   tree_free(ctx, t->b64);
   tree_free(ctx, t->b32);
-  DevBuf* extra[] = {&t->cstat, &t->st,         &t->chains_dev, &t->cnt,    &t->leaves_dev,
-                     &t->path_off_dev, &t->path_dev, &t->shift_src, &t->shift_f};
+  DevBuf* extra[] = {&t->cstat,    &t->st,       &t->chains_dev, &t->cnt,     &t->leaves_dev, &t->path_off_dev,
+                     &t->path_dev, &t->shift_src, &t->shift_f,   &t->n_stage, &t->n_parent,   &t->n_crp,
+                     &t->n_cci,    &t->n_perm,   &t->d_dev,      &t->a2_dev,  &t->q_dev,      &t->broot0,
+                     &t->obj_part, &t->obj_out};
   for (DevBuf* b : extra) ctx->release(*b);
   t->sys->n_trees--;
   delete t;
@@ -1371,16 +1590,46 @@ int smpc_tree_set_data(smpc_tree* t, const double* d, const double* alpha2) {
   if (s->nd > 0 && !d) return set_error(SMPC_EINVAL, "d is NULL");
   if (d && !all_finite(d, (size_t)t->M * s->nd)) return set_error(SMPC_ENAN, "NaN or Inf in d");
   if (alpha2 && !all_finite(alpha2, (size_t)t->N * s->nu)) return set_error(SMPC_ENAN, "NaN or Inf in alpha2");
-  std::vector<double> zero;
-  if (!d) {
-    zero.assign((size_t)t->M * std::max(1, s->nd), 0.0);
-    d = zero.data();
-  }
-  tree_cost_update(t, d, alpha2);
-  SMPC_TRY(tree_upload_data<double>(t));
-  if (t->b32.allocated) SMPC_TRY(tree_upload_data<float>(t));
+  smpc_ctx* ctx = s->ctx;
+  const size_t nd_bytes = sizeof(double) * (size_t)t->M * s->nd;
+  const size_t a2_bytes = sizeof(double) * (size_t)t->N * s->nu;
+  if (d && nd_bytes) HIP_TRY(hipMemcpyAsync(t->d_dev.ptr, d, nd_bytes, hipMemcpyHostToDevice, ctx->stream));
+  else if (nd_bytes) HIP_TRY(hipMemsetAsync(t->d_dev.ptr, 0, nd_bytes, ctx->stream));
+  if (alpha2) HIP_TRY(hipMemcpyAsync(t->a2_dev.ptr, alpha2, a2_bytes, hipMemcpyHostToDevice, ctx->stream));
+  else HIP_TRY(hipMemsetAsync(t->a2_dev.ptr, 0, a2_bytes, ctx->stream));
+  HIP_TRY(launch_cost_update(s->cview, cost_tree_view(t), ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
   t->has_data = true;
+  t->obj_valid = false;
   return SMPC_OK;
+}
+
+int smpc_tree_get_data(smpc_tree* t, double* uhat, double* e, double* beta) {
+  if (!t) return set_error(SMPC_EINVAL, "tree is NULL");
+  if (!t->has_data) return set_error(SMPC_ENOTFACTORED, "smpc_tree_set_data not called");
+  smpc_ctx* ctx = t->sys->ctx;
+  const int M = t->M;
+  const int nx = t->sys->nx, nu = t->sys->nu;
+  const struct {
+    double* out;
+    const DevBuf* buf;
+    int w;
+  } parts[] = {{uhat, &t->b64.uhat, nu}, {e, &t->b64.e, nx}, {beta, &t->b64.beta, nu}};
+  for (const auto& pt : parts) {
+    if (!pt.out) continue;
+    std::vector<double> h((size_t)M * pt.w);
+    HIP_TRY(hipMemcpyAsync(h.data(), pt.buf->ptr, sizeof(double) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (int in = 0; in < M; ++in)
+      std::memcpy(pt.out + (size_t)t->perm[in] * pt.w, h.data() + (size_t)in * pt.w, sizeof(double) * pt.w);
+  }
+  return SMPC_OK;
+}
+
+int smpc_tree_objective(smpc_tree* t, smpc_objective* out) {
+  if (!t || !out) return set_error(SMPC_EINVAL, "NULL argument");
+  SMPC_TRY(ensure_obj_scratch(t));
+  return tree_objective(t, (double*)t->obj_part.ptr, (double*)t->obj_out.ptr, out);
 }
 
 int smpc_factor(smpc_tree* t, const smpc_factor_opts* o) {
@@ -1631,14 +1880,15 @@ int smpc_solve_step(smpc_tree* t, const double* p, const double* q, const double
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return SMPC_OK;
   };
+  SMPC_TRY(upload_q(t, q));
   if (use32) {
-    SMPC_TRY(upload_root<float>(t, p, q));
+    SMPC_TRY(upload_root<float>(t, p));
     SMPC_TRY(put(float{}));
     SMPC_TRY(enqueue_iteration<float>(ctx, s, t->plan, kModeSolve));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     SMPC_TRY(download_primal<float>(t, x, u, nullptr));
   } else {
-    SMPC_TRY(upload_root<double>(t, p, q));
+    SMPC_TRY(upload_root<double>(t, p));
     SMPC_TRY(put(double{}));
     SMPC_TRY(enqueue_iteration<double>(ctx, s, t->plan, kModeSolve));
     HIP_TRY(hipStreamSynchronize(ctx->stream));

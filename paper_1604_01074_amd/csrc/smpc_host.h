@@ -76,6 +76,7 @@ struct smpc_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::map<std::string, std::pair<int, double>> stats;
   int ctab_gen = 0;  // bumped whenever ctab is reallocated (captured graphs hold its address)
+  std::vector<double> ctab_host;  // host copy of ctab
   // cached batch launch plan
   struct Plan* batch_plan = nullptr;
 
@@ -106,6 +107,9 @@ struct smpc_sys {
   int a_identity = 0;
   SysBuffers<double> d64;
   SysBuffers<float> d32;
+  // float64 matrices of the cost update and the objectives (dense Mu, Wu, Gd)
+  smpc::DevBuf c_Mu, c_Wu, c_Gd, c_alpha1;
+  smpc::CostSysDev cview{};
   bool has32 = false;
   int n_trees = 0;
   // chunk lengths {backward, forward} chosen by the last tuned solve, per
@@ -134,9 +138,6 @@ struct smpc_tree {
   std::vector<int32_t> leaves;    // chains that end at a leaf
   std::vector<int32_t> path_off;  // per chain: range in `path`
   std::vector<int32_t> path;      // ancestor nodes of each leaf chain (root first); -1-node = owned
-  // float64 host copies of the per-node data, internal order
-  std::vector<double> beta0;  // beta with q = 0 (root term added per solve)
-  std::vector<double> uhat, e, pi;
   std::vector<double> scale;  // M x 3 or empty
   bool has_data = false;
   bool factored = false;
@@ -146,6 +147,13 @@ struct smpc_tree {
   TreeBuffers<double> b64;
   TreeBuffers<float> b32;
   smpc::DevBuf cstat, st, chains_dev, cnt, leaves_dev, path_off_dev, path_dev;
+  // node structure and inputs of the device cost update (internal order,
+  // demands in the caller's order through perm)
+  smpc::DevBuf n_stage, n_parent, n_crp, n_cci, n_perm, d_dev, a2_dev, q_dev, broot0;
+  // objective partial sums (kObjSlots per workgroup) and results
+  smpc::DevBuf obj_part, obj_out;
+  bool obj_valid = false;  // obj_cache holds the objectives of the resident solve
+  smpc_objective obj_cache{};
   struct Plan* plan = nullptr;  // single-tree launch plan
   // resident dual of the last solve (slot of y^{nu+1} and its precision;
   // -1 when no solve has left one) and a pending warm-start shift
@@ -205,10 +213,17 @@ void choose_chunks(const smpc_sys* sys, const smpc_solve_opts* o, bool from_sys,
                    bool (&tuned)[2]);
 void result_chunks(const int (&chunk)[2][2], const smpc_solve_opts* o, smpc_result* r);
 int read_done(smpc_ctx* ctx, Plan* p);
+int ensure_single_plan(smpc_tree* t, bool need32);
+// Device bytes of a tree's float32 buffers and of a system's float32 copy,
+// and the release of a tree's float32 buffers (with the plans that use them).
+size_t tree32_bytes(const smpc_tree* t);
+size_t sys32_bytes(const smpc_sys* s);
+int tree_release32(smpc_tree* t);
+CostTreeDev cost_tree_view(smpc_tree* t);
+int upload_q(smpc_tree* t, const double* q);
+int tree_objective(smpc_tree* t, double* part, double* out_dev, smpc_objective* out);
 
 // smpc_setup.cpp
 int sys_factor(smpc_sys* s);
-void tree_cost_update(smpc_tree* t, const double* d, const double* alpha2);
-void root_beta(const smpc_tree* t, const double* q, std::vector<double>& out);
 void single_branch_precond(const smpc_sys* s, int N, std::vector<double>& diag);  // N x 3
 }  // namespace smpc

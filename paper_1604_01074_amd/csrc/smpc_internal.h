@@ -167,6 +167,85 @@ template <typename Ts, typename Td>
 hipError_t launch_shift(const Ts* src, Td* dst0, Td* dst2, const int32_t* src_node, const double* f, int M,
                         int nx, int nu, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Float64 node data and objective kernels (smpc_data.hip).
+//
+// System matrices of the cost update of App. A and of the objectives.
+struct CostSysDev {
+  int32_t nx, nu, nd;
+  int32_t safety_by_prob;
+  const double* Mu;      // nu x nd: uhat = Mu d (minimum-norm solution of E u + Ed d = 0)
+  const double* Wu;      // nu x nu
+  const double* Gd;      // nx x nd (dense)
+  const int32_t* b_rp;   // B (CSR)
+  const int32_t* b_ci;
+  const double* b_v;
+  const double* alpha1;  // nu
+  const double* umin;
+  const double* umax;
+  const double* xmin;
+  const double* xmax;
+  const double* xs;
+  double W_alpha, W_x, gamma_d;
+};
+
+// Per-tree node structure and inputs of the cost update, internal node order.
+struct CostTreeDev {
+  int32_t M, N;
+  int32_t root;              // internal index of the root
+  int32_t pad;
+  const int32_t* stage;      // M
+  const int32_t* parent;     // M: internal index of the parent, -1 for the root
+  const int32_t* child_rp;   // M + 1: children of internal node n are
+  const int32_t* child_ci;   //   child_ci[child_rp[n] .. child_rp[n + 1])
+  const int32_t* perm;       // M: caller's index of internal node n
+  const double* pi;          // M
+  const double* d;           // M x nd demands, caller's node order
+  const double* alpha2;      // N x nu pumping costs per stage
+  const double* q;           // nu: input before the root (u_{a(root)})
+  double* uhat;              // M x nu   outputs
+  double* e;                 // M x nx
+  double* beta;              // M x nu
+  double* beta_root0;        // nu: the root's beta without its q term
+  float* uhat32;             // float32 copies (nullptr: none)
+  float* e32;
+  float* beta32;
+};
+
+// Iterates of one solve for the objectives (float64, internal order).
+struct ObjDev {
+  const double* z;      // M x (nx + nu): x_n | u_n
+  const double* yn;     // y^{nu+1} (scaled)
+  const double* yc;     // y^nu
+  const double* yp;     // y^{nu-1}
+  const double* scale;  // M x 3
+  double c;             // extrapolation coefficient of the last iteration
+  double lam;           // step size
+};
+
+// Partial sums of the objective kernels: slots per workgroup and the
+// workgroups of one launch at most (the scratch holds kObjSlots * blocks
+// doubles plus kObjSlots results).
+constexpr int kObjSlots = 8;
+constexpr int kObjMaxBlocks = 1024;
+
+// Cost update: uhat, e, beta (root without its q term) of every node, float64
+// and, where the float32 pointers are set, float32.
+hipError_t launch_cost_update(const CostSysDev& s, const CostTreeDev& t, hipStream_t st);
+// The root's beta for the input q in t.q: beta_root0 - 2 pi_root Wu q.
+hipError_t launch_root_beta(const CostSysDev& s, const CostTreeDev& t, hipStream_t st);
+// Objectives at the iterates of a finished solve, reduced into out[0..7]:
+// primal: [0] stage cost of u, [1] soft cost of t, [2] soft cost of x (t = Hz);
+// dual (after a solve step at the unscaled dual, z = z(y)):
+// [3] stage cost of u, [4] <y, H z>, [5] support function of the sets of g,
+// [6] largest violation of dom g*.  `part` holds kObjSlots * blocks doubles.
+hipError_t launch_objective(const CostSysDev& s, const CostTreeDev& t, const ObjDev& o, bool dual, double* part,
+                            int blocks, double* out, hipStream_t st);
+// dst = S src per dual block (M x (2 nx + nu), scale M x 3).
+hipError_t launch_scale_dual(const double* src, double* dst, const double* scale, int M, int nx, int nu,
+                             hipStream_t st);
+hipError_t launch_narrow(const double* src, float* dst, size_t n, hipStream_t st);
+
 // Row stride of the zero-padded P on the device (and of the staged rho rows),
 // and the dynamic LDS of the two kernels.
 __host__ __device__ inline int p_stride(int nu) { return nu <= 64 ? 64 : 128; }

@@ -41,6 +41,7 @@ struct ServerReq {
   double t_submit = 0, t_start = 0, t_done = 0;
   int phase = 0;  // 32 or 64 while iterating
   int fp32_iters = 0, status32 = 0;
+  bool cancel = false;  // smpc_server_cancel on a running request (under the mutex)
   // outcome, written by the worker under the server mutex
   bool done = false;
   int code = SMPC_OK;
@@ -66,6 +67,8 @@ struct smpc_server {
   bool stop = false;
   // worker state
   std::vector<ServerReq*> active;
+  std::map<smpc_tree*, uint64_t> last_done;  // finish order of each tree's last request
+  uint64_t finished = 0;
   Plan* group[2] = {nullptr, nullptr};  // float32, float64 launch groups
   std::vector<smpc_tree*> members[2];
 };
@@ -83,11 +86,49 @@ void finish(smpc_server* S, ServerReq* r, int code, const char* msg) {
   S->cv_done.notify_all();
 }
 
+bool is_active(const smpc_server* S, const smpc_tree* t) {
+  for (const ServerReq* r : S->active)
+    if (r->t == t) return true;
+  return false;
+}
+
+// Device memory for the float32 buffers of the request's tree: they must fit
+// the context's budget and the device's free memory (less a 1/16 reserve).
+// Idle trees give up their float32 buffers, least recently finished first
+// (a tree whose resident dual is float32 keeps them, a warm start may need
+// it).  SMPC_ENOMEM when that is not enough.
+int make_room(smpc_server* S, smpc_tree* t) {
+  if (!phases(&S->o).run32 || t->b32.allocated) return SMPC_OK;
+  smpc_ctx* ctx = S->sys->ctx;
+  const size_t need = tree32_bytes(t) + (S->sys->has32 ? 0 : sys32_bytes(S->sys));
+  while (true) {
+    size_t freeb = 0, total = 0;
+    if (hipMemGetInfo(&freeb, &total) != hipSuccess) return set_error(SMPC_EDEVICE, "hipMemGetInfo failed");
+    const bool budget_ok = ctx->budget == 0 || ctx->used + need <= ctx->budget;
+    if (budget_ok && freeb >= need + total / 16) return SMPC_OK;
+    smpc_tree* victim = nullptr;
+    uint64_t oldest = UINT64_MAX;
+    for (const auto& kv : S->last_done) {
+      smpc_tree* c = kv.first;
+      if (c == t || !c->b32.allocated || c->res_prec == 32 || is_active(S, c)) continue;
+      if (kv.second < oldest) {
+        oldest = kv.second;
+        victim = c;
+      }
+    }
+    if (!victim)
+      return set_error(SMPC_ENOMEM, "float32 buffers of %zu bytes do not fit (budget %zu, used %zu, device free %zu)",
+                       need, ctx->budget, ctx->used, freeb);
+    SMPC_TRY(tree_release32(victim));
+  }
+}
+
 // Load the request's data and start its dual; SMPC_ENOMEM when its tree's
-// float32 buffers do not fit the HBM budget yet.
+// float32 buffers do not fit yet (checked before any data moves).
 int begin_request(smpc_server* S, ServerReq* r) {
   smpc_tree* t = r->t;
   const SolvePhases ph = phases(&S->o);
+  SMPC_TRY(make_room(S, t));
   if (r->has_d) SMPC_TRY(smpc_tree_set_data(t, r->d.data(), r->has_a2 ? r->a2.data() : nullptr));
   SMPC_TRY(tree_check_ready(t, true));
   if (ph.run32) SMPC_TRY(prepare32(t));
@@ -147,13 +188,13 @@ void worker_main(smpc_server* S) {
         it = S->queue.erase(it);
       }
     }
+    std::vector<ServerReq*> blocked;
     for (ServerReq* r : start) {
       r->t_start = now_ms();
       const int rc = begin_request(S, r);
       if (rc == SMPC_ENOMEM && !S->active.empty()) {
-        // wait for device memory: back to the head of the queue
-        std::lock_guard<std::mutex> g(S->mu);
-        S->queue.push_front(r);
+        // wait for device memory, ahead of later requests
+        blocked.push_back(r);
         continue;
       }
       if (rc < 0) {
@@ -162,6 +203,10 @@ void worker_main(smpc_server* S) {
       }
       r->phase = ph.run32 ? 32 : 64;
       S->active.push_back(r);
+    }
+    if (!blocked.empty()) {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->queue.insert(S->queue.begin(), blocked.begin(), blocked.end());
     }
     if (!start.empty()) S->restarted[ph.run32 ? 0 : 1] = true;
     if (S->active.empty()) continue;
@@ -186,6 +231,20 @@ void worker_main(smpc_server* S) {
     }
     std::vector<ServerReq*> still;
     for (ServerReq* r : S->active) {
+      bool cancel;
+      {
+        std::lock_guard<std::mutex> g(S->mu);
+        cancel = r->cancel;
+      }
+      if (cancel) {
+        // withdrawn: the tree keeps no resident dual from this request
+        r->t->res_slot = -1;
+        r->t->shift_ready = false;
+        r->t->obj_valid = false;
+        S->last_done[r->t] = ++S->finished;
+        finish(S, r, SMPC_ECANCELED, "request canceled");
+        continue;
+      }
       const int g = r->phase == 32 ? 0 : 1;
       const std::vector<smpc_tree*>& m = S->members[g];
       size_t k = 0;
@@ -220,6 +279,7 @@ void worker_main(smpc_server* S) {
         result_chunks(S->chunk, &S->o, &r->res);
       }
       if (code >= 0) code = r->res.status;
+      S->last_done[r->t] = ++S->finished;
       finish(S, r, code, code < 0 ? last_error_text() : nullptr);
     }
     S->active.swap(still);
@@ -322,6 +382,29 @@ int smpc_server_poll(smpc_server* S, uint64_t ticket, smpc_result* res, int wait
   if (code < 0) return set_error(code, "%s", msg.c_str());
   if (code == SMPC_EDIVERGED) return set_error(code, "iteration diverged");
   return code;
+}
+
+int smpc_server_cancel(smpc_server* S, uint64_t ticket) {
+  if (!S) return set_error(SMPC_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> g(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return set_error(SMPC_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  ServerReq* r = it->second;
+  if (r->done) return SMPC_OK;
+  for (auto q = S->queue.begin(); q != S->queue.end(); ++q)
+    if (*q == r) {
+      // never started
+      S->queue.erase(q);
+      r->t_start = r->t_done = now_ms();
+      r->res.queue_ms = r->t_done - r->t_submit;
+      r->code = SMPC_ECANCELED;
+      r->msg = "request canceled";
+      r->done = true;
+      S->cv_done.notify_all();
+      return SMPC_OK;
+    }
+  r->cancel = true;  // running: the worker ends it after the current block
+  return SMPC_OK;
 }
 
 int smpc_server_destroy(smpc_server* S) {

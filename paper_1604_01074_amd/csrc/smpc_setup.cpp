@@ -1,6 +1,7 @@
-// Float64 host setup: the tree-independent factor products (App. B), the
-// per-node cost update (App. A) and the single-branch dual preconditioner
-// (Sec. IV-D).  Plain loops; run once per system / once per new demand set.
+// Float64 host setup: the tree-independent factor products (App. B) and the
+// single-branch dual preconditioner (Sec. IV-D).  Plain loops; run once per
+// system.  (The per-node cost update of App. A runs on the device,
+// smpc_data.hip.)
 //
 // Input-space form of the factor step.  App. A writes u = L v + uhat with L a
 // basis of ker E and eliminates the coupling; App. B then needs
@@ -167,80 +168,6 @@ int sys_factor(smpc_sys* s) {
       }
   s->a_identity = ident;
   return SMPC_OK;
-}
-
-// Cost update (App. A) in input space, caller node order in, internal order
-// out.  For node n with children c:
-//   uhat_n = Mu d_n,   e_n = B uhat_n + Gd d_n,
-//   beta_n = pi_n W_alpha (alpha1 + alpha2_{s(n)})
-//            + 2 Wu (pibar_n uhat_n - pi_n uhat_{a(n)} - sum_c pi_c uhat_c),
-//   pibar_n = pi_n + sum_c pi_c.
-// The v-space coefficient of App. A is L' beta_n.  For the root the parent
-// input is q; that term (-2 pi_root Wu q) is added per solve by root_beta().
-void tree_cost_update(smpc_tree* t, const double* d, const double* alpha2) {
-  const smpc_sys* s = t->sys;
-  const int M = t->M, nu = s->nu, nx = s->nx, nd = s->nd;
-  std::vector<double> uh((size_t)M * nu), ee((size_t)M * nx);
-  for (int n = 0; n < M; ++n) {
-    const double* dn = d + (size_t)n * nd;
-    double* un = &uh[(size_t)n * nu];
-    for (int i = 0; i < nu; ++i) {
-      double acc = 0.0;
-      for (int k = 0; k < nd; ++k) acc += s->Mu[(size_t)i * nd + k] * dn[k];
-      un[i] = acc;
-    }
-    double* en = &ee[(size_t)n * nx];
-    for (int i = 0; i < nx; ++i) {
-      double acc = 0.0;
-      for (int k = 0; k < nu; ++k) acc += s->B[(size_t)i * nu + k] * un[k];
-      for (int k = 0; k < nd; ++k) acc += s->Gd[(size_t)i * nd + k] * dn[k];
-      en[i] = acc;
-    }
-  }
-  // mixing vector m_n = pibar_n uhat_n - pi_n uhat_{a(n)} - sum_c pi_c uhat_c
-  std::vector<double> mix((size_t)M * nu, 0.0), pibar(t->prob);
-  for (int n = 1; n < M; ++n) pibar[t->parent[n]] += t->prob[n];
-  for (int n = 0; n < M; ++n)
-    for (int i = 0; i < nu; ++i) mix[(size_t)n * nu + i] += pibar[n] * uh[(size_t)n * nu + i];
-  for (int n = 1; n < M; ++n) {
-    const int a = t->parent[n];
-    for (int i = 0; i < nu; ++i) {
-      mix[(size_t)n * nu + i] -= t->prob[n] * uh[(size_t)a * nu + i];
-      mix[(size_t)a * nu + i] -= t->prob[n] * uh[(size_t)n * nu + i];
-    }
-  }
-  t->beta0.assign((size_t)M * nu, 0.0);
-  t->uhat.assign((size_t)M * nu, 0.0);
-  t->e.assign((size_t)M * nx, 0.0);
-  std::vector<double> lin(nu);
-  for (int n = 0; n < M; ++n) {
-    const int in = t->iperm[n];
-    const double pin = t->prob[n];
-    const double* a2 = alpha2 ? alpha2 + (size_t)t->stage[n] * nu : nullptr;
-    for (int i = 0; i < nu; ++i) lin[i] = s->W_alpha * (s->alpha1[i] + (a2 ? a2[i] : 0.0));
-    double* bo = &t->beta0[(size_t)in * nu];
-    const double* mn = &mix[(size_t)n * nu];
-    for (int i = 0; i < nu; ++i) {
-      double acc = 0.0;
-      for (int k = 0; k < nu; ++k) acc += s->Wu[(size_t)i * nu + k] * mn[k];
-      bo[i] = pin * lin[i] + 2.0 * acc;
-    }
-    std::memcpy(&t->uhat[(size_t)in * nu], &uh[(size_t)n * nu], sizeof(double) * nu);
-    std::memcpy(&t->e[(size_t)in * nx], &ee[(size_t)n * nx], sizeof(double) * nx);
-  }
-}
-
-void root_beta(const smpc_tree* t, const double* q, std::vector<double>& out) {
-  const smpc_sys* s = t->sys;
-  const int nu = s->nu;
-  const int r = t->iperm[0];
-  out.assign(t->beta0.begin() + (size_t)r * nu, t->beta0.begin() + (size_t)(r + 1) * nu);
-  const double pr = t->prob[0];
-  for (int i = 0; i < nu; ++i) {
-    double acc = 0.0;
-    for (int k = 0; k < nu; ++k) acc += s->Wu[(size_t)i * nu + k] * q[k];
-    out[i] -= 2.0 * pr * acc;
-  }
 }
 
 // Diagonal of the dual Hessian for one branch of the tree (a chain of N

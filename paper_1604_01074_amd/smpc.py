@@ -18,21 +18,21 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsmpc.so")
 
 OK, MAX_ITER, PENDING = 0, 1, 2
-EINVAL, EDIM, ENOTSPD, ERANK, EPROB, ENOMEM, EDEVICE, ENOTFACTORED, EDIVERGED, ENAN = range(-1, -11, -1)
+EINVAL, EDIM, ENOTSPD, ERANK, EPROB, ENOMEM, EDEVICE, ENOTFACTORED, EDIVERGED, ENAN, ECANCELED = range(-1, -12, -1)
 STATUS_NAMES = {
     0: "SMPC_OK", 1: "SMPC_MAX_ITER", 2: "SMPC_PENDING", -1: "SMPC_EINVAL", -2: "SMPC_EDIM", -3: "SMPC_ENOTSPD",
     -4: "SMPC_ERANK", -5: "SMPC_EPROB", -6: "SMPC_ENOMEM", -7: "SMPC_EDEVICE",
-    -8: "SMPC_ENOTFACTORED", -9: "SMPC_EDIVERGED", -10: "SMPC_ENAN",
+    -8: "SMPC_ENOTFACTORED", -9: "SMPC_EDIVERGED", -10: "SMPC_ENAN", -11: "SMPC_ECANCELED",
 }
 
 EXPORTED = [
     "smpc_ctx_create", "smpc_ctx_destroy", "smpc_last_error", "smpc_ctx_mem_used",
     "smpc_sys_create", "smpc_sys_destroy",
-    "smpc_tree_create", "smpc_tree_destroy", "smpc_tree_set_data",
+    "smpc_tree_create", "smpc_tree_destroy", "smpc_tree_set_data", "smpc_tree_get_data", "smpc_tree_objective",
     "smpc_factor", "smpc_tree_get_factor", "smpc_tree_info",
     "smpc_solve", "smpc_solve_batch", "smpc_shift_warm_start", "smpc_solve_step",
     "smpc_ctx_set_profiling", "smpc_ctx_kernel_stats", "smpc_ctx_reset_stats",
-    "smpc_server_create", "smpc_server_submit", "smpc_server_poll", "smpc_server_destroy",
+    "smpc_server_create", "smpc_server_submit", "smpc_server_poll", "smpc_server_cancel", "smpc_server_destroy",
     "smpc_chunk_lengths",
 ]
 
@@ -82,14 +82,19 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("precision", C.c_int), ("polish_iters", C.c_int), ("warm_start", C.c_int),
                 ("y0", _dp), ("y_prev0", _dp), ("stall_checks", C.c_int), ("tune", C.c_int),
-                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2), ("unfused", C.c_int)]
+                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2), ("unfused", C.c_int), ("gap", C.c_int)]
 
 
 class Result(C.Structure):
     _fields_ = [("u0", _dp), ("x", _dp), ("u", _dp), ("y", _dp), ("iterations", C.c_int),
                 ("fp32_iterations", C.c_int), ("r_primal", C.c_double), ("hz_t_max", C.c_double),
                 ("status", C.c_int), ("queue_ms", C.c_double), ("run_ms", C.c_double),
-                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2)]
+                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2), ("cost", C.c_double), ("gap", C.c_double)]
+
+
+class Objective(C.Structure):
+    _fields_ = [("cost", C.c_double), ("primal", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
+                ("dual_violation", C.c_double)]
 
 
 class ServerOpts(C.Structure):
@@ -110,6 +115,8 @@ _sig = {
     "smpc_tree_create": [_vp, C.c_int, C.c_int, _ip, _ip, _dp, C.POINTER(_vp)],
     "smpc_tree_destroy": [_vp],
     "smpc_tree_set_data": [_vp, _dp, _dp],
+    "smpc_tree_get_data": [_vp, _dp, _dp, _dp],
+    "smpc_tree_objective": [_vp, C.POINTER(Objective)],
     "smpc_factor": [_vp, C.POINTER(FactorOpts)],
     "smpc_tree_get_factor": [_vp, _dp, _dp],
     "smpc_tree_info": [_vp, _ip, _ip, _ip, _ip],
@@ -124,6 +131,7 @@ _sig = {
     "smpc_server_create": [_vp, C.POINTER(ServerOpts), C.POINTER(_vp)],
     "smpc_server_submit": [_vp, _vp, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.POINTER(C.c_uint64)],
     "smpc_server_poll": [_vp, C.c_uint64, C.POINTER(Result), C.c_int],
+    "smpc_server_cancel": [_vp, C.c_uint64],
     "smpc_server_destroy": [_vp],
     "smpc_chunk_lengths": [C.c_int, C.c_int, _ip, C.c_int, _ip],
 }
@@ -226,6 +234,21 @@ def smpc_tree_set_data(t, d, alpha2=None) -> None:
     _check(_lib.smpc_tree_set_data(t, _ptr(dd), _ptr(a2)))
 
 
+def smpc_tree_get_data(t, *, dims) -> dict:
+    """uhat (M, nu), e (M, nx), beta (M, nu) as held on the device."""
+    M, nx, nu = dims
+    out = {"uhat": np.empty((M, nu)), "e": np.empty((M, nx)), "beta": np.empty((M, nu))}
+    _check(_lib.smpc_tree_get_data(t, _ptr(out["uhat"]), _ptr(out["e"]), _ptr(out["beta"])))
+    return out
+
+
+def smpc_tree_objective(t) -> dict:
+    """cost, primal, dual, gap, dual_violation at the tree's last solve."""
+    o = Objective()
+    _check(_lib.smpc_tree_objective(t, C.byref(o)))
+    return {k: getattr(o, k) for k in ("cost", "primal", "dual", "gap", "dual_violation")}
+
+
 def smpc_factor(t, precond: int = 0, power_iters: int = 0, lambda_override: float = 0.0, scale=None) -> None:
     sc = None if scale is None else _f64(scale)
     o = FactorOpts(int(precond), int(power_iters), float(lambda_override), _ptr(sc))
@@ -256,14 +279,14 @@ def _pair(v):
 
 
 def _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks=0, resident=False,
-          tune=0, chunk32=None, chunk64=None, unfused=False):
+          tune=0, chunk32=None, chunk64=None, unfused=False, gap=False):
     keep = [None if y0 is None else _f64(y0), None if y_prev0 is None else _f64(y_prev0)]
     if resident and y0 is not None:
         raise ValueError("a resident warm start and y0 exclude each other")
     warm = 1 if resident else (2 if y0 is not None else 0)
     o = SolveOpts(float(tol), int(max_iter), int(check_every), int(precision), int(polish_iters),
                   warm, _ptr(keep[0]), _ptr(keep[1]), int(stall_checks), int(tune), _pair(chunk32),
-                  _pair(chunk64), int(bool(unfused)))
+                  _pair(chunk64), int(bool(unfused)), int(bool(gap)))
     return o, keep
 
 
@@ -281,18 +304,20 @@ def _result(M, nx, nu, want_x, want_y):
 
 def _finish(r: Result, out: dict) -> dict:
     out.update(iterations=r.iterations, fp32_iterations=r.fp32_iterations, r_primal=r.r_primal,
-               hz_t_max=r.hz_t_max, status=r.status, chunk32=tuple(r.chunk32), chunk64=tuple(r.chunk64))
+               hz_t_max=r.hz_t_max, status=r.status, chunk32=tuple(r.chunk32), chunk64=tuple(r.chunk64),
+               cost=r.cost, gap=r.gap)
     return out
 
 
 def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precision=64, polish_iters=0,
                y0=None, y_prev0=None, want_x=True, want_y=True, stall_checks=0, resident=False, tune=0,
-               chunk32=None, chunk64=None, unfused=False) -> dict:
+               chunk32=None, chunk64=None, unfused=False, gap=False) -> dict:
     """``dims = (M, nx, nu)``.  Returns a dict with u0, x, u, y, iterations,
-    fp32_iterations, r_primal, hz_t_max, status, chunk32, chunk64."""
+    fp32_iterations, r_primal, hz_t_max, status, chunk32, chunk64, cost, gap
+    (the last two with ``gap=True``)."""
     M, nx, nu = dims
     o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident,
-                    tune, chunk32, chunk64, unfused)
+                    tune, chunk32, chunk64, unfused, gap)
     r, out = _result(M, nx, nu, want_x, want_y)
     pp, qq = _f64(p), _f64(q)
     _check_solve(_lib.smpc_solve(t, _ptr(pp), _ptr(qq), C.byref(o), C.byref(r)))
@@ -302,10 +327,10 @@ def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precis
 def smpc_solve_batch(trees, ps, qs, *, dims_list, tol=1e-3, max_iter=1000, check_every=10, precision=64,
                      polish_iters=0, y0=None, y_prev0=None, want_x=True, want_y=True,
                      stall_checks=0, resident=False, tune=0, chunk32=None, chunk64=None,
-                     unfused=False) -> tuple[int, list]:
+                     unfused=False, gap=False) -> tuple[int, list]:
     n = len(trees)
     o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident,
-                    tune, chunk32, chunk64, unfused)
+                    tune, chunk32, chunk64, unfused, gap)
     res = (Result * n)()
     outs = []
     for k, (M, nx, nu) in enumerate(dims_list):
@@ -386,17 +411,24 @@ def smpc_server_submit(srv, tree, p, q, *, d=None, alpha2=None, warm=0, realized
 
 def smpc_server_poll(srv, ticket: int, nu: int, wait_ms: int = -1):
     """None while the request runs, else a dict with u0, iterations,
-    fp32_iterations, r_primal, hz_t_max, status, queue_ms, run_ms."""
+    fp32_iterations, r_primal, hz_t_max, status, queue_ms, run_ms (only
+    status and the times for a canceled request)."""
     u0 = np.empty(nu)
     r = Result(_ptr(u0), None, None, None)
     code = _lib.smpc_server_poll(srv, C.c_uint64(ticket), C.byref(r), int(wait_ms))
     if code == PENDING:
         return None
-    if code < 0 and code != EDIVERGED:
+    if code < 0 and code not in (EDIVERGED, ECANCELED):
         raise SmpcError(code, last_error())
+    if code == ECANCELED:
+        return dict(status=code, queue_ms=r.queue_ms, run_ms=r.run_ms)
     return dict(u0=u0, iterations=r.iterations, fp32_iterations=r.fp32_iterations, r_primal=r.r_primal,
                 hz_t_max=r.hz_t_max, status=r.status, queue_ms=r.queue_ms, run_ms=r.run_ms,
                 chunk32=tuple(r.chunk32), chunk64=tuple(r.chunk64))
+
+
+def smpc_server_cancel(srv, ticket: int) -> None:
+    _check(_lib.smpc_server_cancel(srv, C.c_uint64(ticket)))
 
 
 def smpc_server_destroy(srv) -> None:

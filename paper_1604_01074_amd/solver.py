@@ -93,6 +93,12 @@ class Tree:
     def set_data(self, d, alpha2=None) -> None:
         S.smpc_tree_set_data(self.h, d, alpha2)
 
+    def get_data(self) -> dict:
+        return S.smpc_tree_get_data(self.h, dims=self.dims)
+
+    def objective(self) -> dict:
+        return S.smpc_tree_objective(self.h)
+
     def factor(self, **kw) -> None:
         S.smpc_factor(self.h, **kw)
 
@@ -139,6 +145,9 @@ class Server:
 
     def poll(self, ticket: int, wait_ms: int = -1):
         return S.smpc_server_poll(self.h, ticket, self.system.nu, wait_ms)
+
+    def cancel(self, ticket: int) -> None:
+        S.smpc_server_cancel(self.h, ticket)
 
     def close(self) -> None:
         if self.h is not None:

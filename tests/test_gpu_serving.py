@@ -99,23 +99,108 @@ def test_server_errors(setup):
     from paper_1604_01074_amd import smpc, solver
 
     system, insts, trees = setup
+    # trees are built before the server exists (afterwards they are used only
+    # through it)
+    fresh = system.tree(insts[4].tree)
+    fresh.set_data(insts[4].d, insts[4].alpha2)
+    fresh.factor(precond=1, power_iters=20)
+    other = system.ctx.system(ds.tiny_tank_system(0))
+    tiny = ds.tiny_instance()
+    ot = other.tree(tiny.tree)
     srv = system.server(**KW)
     try:
         with pytest.raises(smpc.SmpcError) as e:
             srv.poll(12345, wait_ms=0)
         assert e.value.code == smpc.EINVAL
-        other = system.ctx.system(ds.tiny_tank_system(0))
-        tiny = ds.tiny_instance()
-        ot = other.tree(tiny.tree)
         with pytest.raises(smpc.SmpcError) as e:
             srv.submit(ot, tiny.p, tiny.q)  # a tree of another system
         assert e.value.code == smpc.EINVAL
-        fresh = system.tree(insts[4].tree)
-        fresh.set_data(insts[4].d, insts[4].alpha2)
-        fresh.factor(precond=1, power_iters=20)
         tk = srv.submit(fresh, insts[4].p, insts[4].q, warm=1, realized=0)  # nothing resident
         with pytest.raises(smpc.SmpcError) as e:
             srv.poll(tk)
         assert e.value.code == smpc.EINVAL
     finally:
         srv.close()
+
+
+def test_server_cancel(setup):
+    """A withdrawn request reports SMPC_ECANCELED, queued or running; the
+    other requests are unaffected and equal their direct solves."""
+    from paper_1604_01074_amd import smpc
+
+    system, insts, trees = setup
+    ref = trees[2].solve(insts[2].p, insts[2].q, want_x=False, want_y=False, **KW)
+    srv = system.server(max_active=1, **KW)
+    try:
+        t0 = srv.submit(trees[0], insts[0].p, insts[0].q)    # runs first
+        t1 = srv.submit(trees[1], insts[1].p, insts[1].q)    # queued behind it
+        t2 = srv.submit(trees[2], insts[2].p, insts[2].q)
+        srv.cancel(t1)
+        srv.cancel(t0)
+        r0, r1, r2 = srv.poll(t0), srv.poll(t1), srv.poll(t2)
+    finally:
+        srv.close()
+    assert r1["status"] == smpc.ECANCELED
+    # the first request was running (or had just finished) when canceled
+    assert r0["status"] in (smpc.ECANCELED, smpc.OK, smpc.MAX_ITER)
+    _same(r2, ref)
+
+
+def test_server_waits_for_memory_then_admits(lib_free_ctx):
+    """Back-pressure: with an HBM budget that holds the float32 buffers of
+    one tree at a time, requests for three trees all complete -- each waits
+    until the previous tree is idle and gives its float32 buffers up -- and
+    each result equals the direct solve of the same tree bit for bit."""
+    from paper_1604_01074_amd import solver
+
+    sysd = ds.barcelona_shaped_system(1)
+    shapes = [(6, (3, 2)), (8, (2, 2, 2)), (7, (3, 3))]
+    insts = [ds.barcelona_instance(N=N, branching=b, sys=sysd, demand_seed=30 + k) for k, (N, b) in enumerate(shapes)]
+
+    def build(ctx):
+        system = ctx.system(sysd)
+        trees = []
+        for inst in insts:
+            t = system.tree(inst.tree)
+            t.set_data(inst.d, inst.alpha2)
+            t.factor(precond=1, power_iters=100)
+            trees.append(t)
+        return system, trees
+
+    # footprint without float32 buffers, and with each tree's; the probe's
+    # solves are the references
+    probe = solver.Context(0)
+    system, trees = build(probe)
+    base = probe.mem_used()
+    used32, ref = [], []
+    for t, inst in zip(trees, insts):
+        before = probe.mem_used()
+        ref.append(t.solve(inst.p, inst.q, want_x=False, want_y=False, **KW))
+        used32.append(probe.mem_used() - before)
+    probe.close()
+    budget = base + max(used32) + min(used32) // 2  # one tree's float32 buffers at a time
+    print(f"[serve-mem] base {base} float32 {used32} budget {budget}", flush=True)
+    ctx = solver.Context(0, hbm_budget=budget)
+    try:
+        system, trees = build(ctx)
+        srv = system.server(max_active=3, **KW)
+        try:
+            tickets = [srv.submit(t, i.p, i.q) for t, i in zip(trees, insts)]
+            got = [srv.poll(tk) for tk in tickets]
+        finally:
+            srv.close()
+        assert ctx.mem_used() <= budget
+        for a, b in zip(got, ref):
+            _same(a, b)
+        # each later request waited for the one before it to finish
+        for k in (1, 2):
+            assert got[k]["queue_ms"] >= 0.5 * got[k - 1]["run_ms"], [(g["queue_ms"], g["run_ms"]) for g in got]
+    finally:
+        ctx.close()
+
+
+@pytest.fixture
+def lib_free_ctx():
+    from paper_1604_01074_amd import solver  # noqa: F401  (fails loudly if not built)
+
+    yield None
