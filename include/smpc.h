@@ -295,6 +295,19 @@ typedef struct {
   double dual_violation;
 } smpc_objective;
 int smpc_tree_objective(smpc_tree* tree, smpc_objective* out);
+/* smpc_tree_objective for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with the partial sums in a
+ * fixed device array of the library (8 * 1025 doubles, 65.6 KB per GPU,
+ * held until the process ends; the kernels stride over the nodes, so every
+ * tree size fits).  Calls no hipMalloc / hipFree and records no profiling
+ * events.  Needs the tree's single-tree launch plan, which smpc_solve of
+ * that tree and smpc_factor's power iteration create (SMPC_EINVAL otherwise:
+ * a tree factored with lambda_override and solved only in batches has
+ * none).  Every call on one GPU shares the array: calls that overlap on a
+ * GPU (other host threads, other contexts) race and must be serialised by
+ * the caller.                                                              */
+int smpc_tree_objective_noalloc(smpc_tree* tree, smpc_objective* out);
 
 /* ------------------------------------------------------------------ serving
  * Continuous batching of closed-loop MPC steps (the loop of Alg. 2 for many

@@ -1632,6 +1632,22 @@ int smpc_tree_objective(smpc_tree* t, smpc_objective* out) {
   return tree_objective(t, (double*)t->obj_part.ptr, (double*)t->obj_out.ptr, out);
 }
 
+int smpc_tree_objective_noalloc(smpc_tree* t, smpc_objective* out) {
+  if (!t || !out) return set_error(SMPC_EINVAL, "NULL argument");
+  if (t->res_slot >= 0 && !t->obj_valid && !t->plan)
+    return set_error(SMPC_EINVAL, "the tree has no single-tree launch plan (a smpc_solve of this tree creates it)");
+  smpc_ctx* ctx = t->sys->ctx;
+  double* sc = nullptr;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(objective_scratch(&sc));
+  // no profiling events either: the kernels run untimed
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;
+  const int rc = tree_objective(t, sc, sc + (size_t)kObjSlots * kObjMaxBlocks, out);
+  ctx->profiling = prof;
+  return rc;
+}
+
 int smpc_factor(smpc_tree* t, const smpc_factor_opts* o) {
   if (t) {
     t->res_slot = -1;  // the power iteration overwrites the dual slots

@@ -10,9 +10,15 @@
 //                                Sec. IV-E, reduced in a fixed order
 //   k_scale_dual, k_narrow       element-wise helpers
 //
+// The objective kernels take their partial sums from a caller-provided
+// buffer: a per-tree allocation (smpc_tree_objective) or the file-scope
+// `scratch` array (smpc_tree_objective_noalloc).
+//
 // One workgroup of 128 threads per node (grid-stride): thread j handles input
 // component j and state component j (nx, nu <= 128).  Node arrays are in the
 // library's internal (chain-major) order.
+#include <mutex>
+
 #include "smpc_internal.h"
 
 namespace smpc {
@@ -314,7 +320,33 @@ int grid_for(size_t n, int block) {
   return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
 }
 
+// Device scratch of the no-allocation objective entry point: the partial
+// sums of up to kObjMaxBlocks workgroups and the kObjSlots results.  Each GPU
+// holds its own copy for the life of the process; every call on a GPU
+// shares it.
+static __device__ __align__(256) double scratch[kObjSlots * (kObjMaxBlocks + 1)];
+
 }  // namespace
+
+// The device address of `scratch` on the current device, looked up once per
+// device (the array's name in host code is not a device address).
+hipError_t objective_scratch(double** ptr) {
+  static std::mutex mu;
+  static double* addr[64] = {nullptr};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_cost_update(const CostSysDev& s, const CostTreeDev& t, hipStream_t st) {
   const int grid = t.M < 8192 ? t.M : 8192;

@@ -222,6 +222,9 @@ int tree_release32(smpc_tree* t);
 CostTreeDev cost_tree_view(smpc_tree* t);
 int upload_q(smpc_tree* t, const double* q);
 int tree_objective(smpc_tree* t, double* part, double* out_dev, smpc_objective* out);
+// The device address of the no-allocation objective scratch on the current
+// device (smpc_data.hip): kObjSlots * (kObjMaxBlocks + 1) doubles.
+hipError_t objective_scratch(double** ptr);
 
 // smpc_setup.cpp
 int sys_factor(smpc_sys* s);

@@ -29,6 +29,7 @@ EXPORTED = [
     "smpc_ctx_create", "smpc_ctx_destroy", "smpc_last_error", "smpc_ctx_mem_used",
     "smpc_sys_create", "smpc_sys_destroy",
     "smpc_tree_create", "smpc_tree_destroy", "smpc_tree_set_data", "smpc_tree_get_data", "smpc_tree_objective",
+    "smpc_tree_objective_noalloc",
     "smpc_factor", "smpc_tree_get_factor", "smpc_tree_info",
     "smpc_solve", "smpc_solve_batch", "smpc_shift_warm_start", "smpc_solve_step",
     "smpc_ctx_set_profiling", "smpc_ctx_kernel_stats", "smpc_ctx_reset_stats",
@@ -117,6 +118,7 @@ _sig = {
     "smpc_tree_set_data": [_vp, _dp, _dp],
     "smpc_tree_get_data": [_vp, _dp, _dp, _dp],
     "smpc_tree_objective": [_vp, C.POINTER(Objective)],
+    "smpc_tree_objective_noalloc": [_vp, C.POINTER(Objective)],
     "smpc_factor": [_vp, C.POINTER(FactorOpts)],
     "smpc_tree_get_factor": [_vp, _dp, _dp],
     "smpc_tree_info": [_vp, _ip, _ip, _ip, _ip],
@@ -246,6 +248,14 @@ def smpc_tree_objective(t) -> dict:
     """cost, primal, dual, gap, dual_violation at the tree's last solve."""
     o = Objective()
     _check(_lib.smpc_tree_objective(t, C.byref(o)))
+    return {k: getattr(o, k) for k in ("cost", "primal", "dual", "gap", "dual_violation")}
+
+
+def smpc_tree_objective_noalloc(t) -> dict:
+    """smpc_tree_objective with the library's fixed device scratch (no
+    device allocation)."""
+    o = Objective()
+    _check(_lib.smpc_tree_objective_noalloc(t, C.byref(o)))
     return {k: getattr(o, k) for k in ("cost", "primal", "dual", "gap", "dual_violation")}
 
 
