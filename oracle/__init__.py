@@ -28,6 +28,8 @@ from .smpc_oracle import (
     dual_lmax_power,
     shift_map,
     shift_dual,
+    plant_step,
+    closed_loop_kpis,
 )
 
 __all__ = [
@@ -51,4 +53,6 @@ __all__ = [
     "dual_lmax_power",
     "shift_map",
     "shift_dual",
+    "plant_step",
+    "closed_loop_kpis",
 ]

@@ -617,3 +617,33 @@ def shift_dual(P: OracleProblem, y: np.ndarray, realized: int) -> np.ndarray:
         out[:, :nx] *= ratio[:, None]
     out[:, 2 * nx:] *= ratio[:, None]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Closed loop (Alg. 2) and its performance indicators (Sec. V-B)
+# ---------------------------------------------------------------------------
+def plant_step(P: OracleProblem, x: np.ndarray, u: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """One step of the flow model (eq. model): ``x+ = A x + B u + Gd d``."""
+    return P.A @ x + P.B @ u + P.Gd @ d
+
+
+def closed_loop_kpis(alpha1: np.ndarray, alpha2: np.ndarray, xs: np.ndarray, x: np.ndarray, u: np.ndarray,
+                     u_prev: np.ndarray) -> dict:
+    """The four indicators of Sec. V-B over a simulation of ``Hs`` steps:
+    ``alpha2`` (Hs, nu) the pumping cost of each applied step, ``u`` (Hs, nu)
+    the applied inputs, ``x`` (Hs, nx) the states they lead to, ``u_prev``
+    the input applied before the first step.
+
+    * KPI_E  = (1/Hs) sum_k (alpha1 + alpha2_k)' |u_k|      (economic cost)
+    * KPI_dU = (1/Hs) sum_k ||u_k - u_{k-1}||_2^2           (smoothness)
+    * KPI_S  = sum_k ||[xs - x_k]_+||_1                     (water taken from the safety storage)
+    * KPI_R  = ||xs||_1 / ((1/Hs) sum_k ||x_k||_1) * 100    (safety volume in % of the mean volume)
+    """
+    Hs = u.shape[0]
+    e = sum(float((alpha1 + alpha2[k]) @ np.abs(u[k])) for k in range(Hs)) / Hs
+    prev = np.vstack([u_prev[None, :], u[:-1]])
+    du = sum(float(np.sum((u[k] - prev[k]) ** 2)) for k in range(Hs)) / Hs
+    s = sum(float(np.sum(np.maximum(xs - x[k], 0.0))) for k in range(Hs))
+    mean_vol = sum(float(np.sum(np.abs(x[k]))) for k in range(Hs)) / Hs
+    r = float(np.sum(np.abs(xs))) / mean_vol * 100.0
+    return {"E": e, "dU": du, "S": s, "R": r}
