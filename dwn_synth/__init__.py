@@ -18,6 +18,7 @@ from .instances import (
     batch_instances,
     random_small_instance,
     barcelona_demands,
+    closed_loop_demands,
     serving_controllers,
     step_demands,
 )
@@ -37,6 +38,7 @@ __all__ = [
     "batch_instances",
     "random_small_instance",
     "barcelona_demands",
+    "closed_loop_demands",
     "serving_controllers",
     "step_demands",
 ]

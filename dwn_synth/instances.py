@@ -123,6 +123,41 @@ BATCH_SHAPES = {16: [4, 4], 64: [4, 4, 4], 125: [5, 5, 5], 343: [7, 7, 7], 512: 
 BATCH_HORIZONS = (12, 18, 24)
 
 
+def closed_loop_demands(sys: dict, tree: dict, hours: int, seed: int = 77):
+    """Demands and pumping costs of ``hours`` closed-loop steps (Alg. 2) of a
+    controller on a Barcelona-shaped system.
+
+    One fixed 24-periodic profile per demand, ``b_k (1 + 0.3 sin(2 pi (h +
+    phi_k) / 24))`` (``b_k``, ``phi_k`` as in ``barcelona_demands``), drawn
+    from ``seed`` alone, so every controller sees the same profile and the
+    same realised demands ``actual[h] = profile(h) exp(0.1 eps_h - 0.005)``.
+    At step ``h`` the tree's root carries ``actual[h]`` (known when u_0 is
+    decided) and a node at stage j the forecast ``profile(h + j)
+    exp(0.1 eps - 0.005)`` with fresh per-node noise.  Returns a list of
+    ``(d, alpha2)``; ``d[0]`` of step h is the demand the plant sees."""
+    M, ne, nd = tree["M"], sys["ne"], sys["nd"]
+    E = sys["E"]
+    prof_rng = np.random.default_rng([seed, 1])
+    base = np.empty(nd)
+    base[ne:] = prof_rng.uniform(0.5, 2.0, nd - ne)
+    inflow = np.array([int(np.flatnonzero(E[r] > 0)[0]) for r in range(ne)], dtype=np.int64)
+    base[:ne] = 0.25 * sys["umax"][inflow]
+    phi = prof_rng.uniform(0.0, 24.0, nd)
+
+    def profile(hours_arr):
+        return base[None, :] * (1.0 + 0.3 * np.sin(2.0 * np.pi * (hours_arr[:, None] + phi[None, :]) / 24.0))
+
+    act_rng = np.random.default_rng([seed, 2])
+    actual = profile(np.arange(hours, dtype=np.float64)) * np.exp(0.1 * act_rng.standard_normal((hours, nd)) - 0.005)
+    out = []
+    for h in range(hours):
+        rng = np.random.default_rng([seed, 3, h])
+        d = profile((h + tree["stage"]).astype(np.float64)) * np.exp(0.1 * rng.standard_normal((M, nd)) - 0.005)
+        d[0] = actual[h]
+        out.append((d, pumping_cost(sys, int(tree["N"]), start_hour=h)))
+    return out
+
+
 def table1_instance(name: str, seed: int = 1, sys: dict | None = None) -> Instance:
     """A Table 1 controller (Sec. V-B: its branching and scenario count, N =
     24) on the Barcelona-shaped system, with demands, pumping cost and initial

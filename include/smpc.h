@@ -190,7 +190,16 @@ int smpc_tree_info(smpc_tree* tree, int* M, int* N, int* n_chains, int* n_levels
  * unfused: 0 -> each APG iteration after the first is one launch (the
  * forward rollout of iteration nu and the backward sweep of iteration nu + 1
  * in the same workgroups); 1 -> two launches per iteration (backward, then
- * forward).  Results are identical.                                         */
+ * forward).  Results are identical.
+ * dual64 (precision 32 only): 1 -> the float32 phase keeps the dual iterates
+ * y^nu, y^{nu-1}, y^{nu+1} in float64 and runs the extrapolation, the prox
+ * and the dual update in float64; the solve step (its matrix-vector
+ * products, the recursions over the tree and the node data) stays float32.
+ * Rounding the stored dual to float32 limits how far the float32 iteration
+ * gets (r_p stalls on some trees), while float32 errors in the solve step
+ * only perturb each dual gradient, so with dual64 the float32 phase follows
+ * the float64 iteration to the tolerance.  The stall rule then applies only
+ * when stall_checks > 0.  0 -> the dual is stored in float32 too.          */
 typedef struct {
   double tol;
   int max_iter;
@@ -206,6 +215,7 @@ typedef struct {
   int chunk64[2];
   int unfused;
   int gap;  /* 1: fill smpc_result.cost and .gap (smpc_tree_objective)   */
+  int dual64;
 } smpc_solve_opts;
 
 /* Chunk lengths built into the library for `precision` (32 or 64) and
@@ -304,10 +314,33 @@ int smpc_tree_objective(smpc_tree* tree, smpc_objective* out);
  * events.  Needs the tree's single-tree launch plan, which smpc_solve of
  * that tree and smpc_factor's power iteration create (SMPC_EINVAL otherwise:
  * a tree factored with lambda_override and solved only in batches has
- * none).  Every call on one GPU shares the array: calls that overlap on a
- * GPU (other host threads, other contexts) race and must be serialised by
+ * none).  Every call on one GPU shares the array: calls that overlap on
+ * a GPU (other host threads, other contexts) race and must be serialised by
  * the caller.                                                              */
 int smpc_tree_objective_noalloc(smpc_tree* tree, smpc_objective* out);
+
+/* ------------------------------------------------------------------ closed loop
+ * The loop of Alg. 2 around the solver: apply u0, move the plant, solve
+ * again.  smpc_plant_step is the flow model of Sec. II (eq. model),
+ *   x_next = A x + B u + Gd d      (x: nx, u: nu, d: nd; float64, host)
+ * with the realised demand d.  smpc_closed_loop_kpi evaluates the key
+ * performance indicators of Sec. V-B over a run of Hs steps: u (Hs*nu) the
+ * applied inputs u_1..u_Hs, x (Hs*nx) the states they lead to, alpha2
+ * (Hs*nu, NULL = zero) the pumping cost of each step, u_prev (nu) the input
+ * before the first step:
+ *   E  = (1/Hs) sum_k (alpha1 + alpha2_k)' |u_k|        average economic cost
+ *   dU = (1/Hs) sum_k ||u_k - u_{k-1}||_2^2              smoothness
+ *   S  = sum_k ||[xs - x_k]_+||_1                        water taken from the
+ *                                                        safety storage
+ *   R  = ||xs||_1 / ((1/Hs) sum_k ||x_k||_1) * 100       safety volume in % of
+ *                                                        the mean volume
+ * Errors: SMPC_EINVAL (NULL, Hs < 1), SMPC_ENAN.                            */
+int smpc_plant_step(smpc_sys* sys, const double* x, const double* u, const double* d, double* x_next);
+typedef struct {
+  double E, dU, S, R;
+} smpc_kpi;
+int smpc_closed_loop_kpi(smpc_sys* sys, int Hs, const double* u, const double* x, const double* alpha2,
+                         const double* u_prev, smpc_kpi* out);
 
 /* ------------------------------------------------------------------ serving
  * Continuous batching of closed-loop MPC steps (the loop of Alg. 2 for many

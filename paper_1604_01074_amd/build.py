@@ -1,7 +1,8 @@
 """Build the HIP/C++ library ``libsmpc.so`` for gfx950 in this directory.
 
 ``python -m paper_1604_01074_amd.build`` (or ``build()``) always recompiles:
-the kernel file twice (float64 and float32 instantiations) and the host
+the kernel file three times (float64, float32 and float32-on-float64-dual
+instantiations) and the host
 sources, in parallel, then one link.
 """
 
@@ -37,15 +38,16 @@ def _output(text: str) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source to an object in parallel (the kernel file twice,
+    """Compile every source to an object in parallel (the kernel file three times,
     one part per precision), then link ``libsmpc.so``."""
     inc = ["-I", os.path.join(HERE, "..", "include")]
     tmpdir = tempfile.mkdtemp(prefix="smpc_build_")
     try:
         jobs = []
         for src, defs in (("smpc_kernels.hip", ["-DSMPC_KERNEL_PART=1"]), ("smpc_kernels.hip", ["-DSMPC_KERNEL_PART=2"]),
+                          ("smpc_kernels.hip", ["-DSMPC_KERNEL_PART=3"]),
                           ("smpc_data.hip", []), ("smpc_setup.cpp", []), ("smpc_api.cpp", []),
-                          ("smpc_server.cpp", [])):
+                          ("smpc_server.cpp", []), ("smpc_loop.cpp", [])):
             obj = os.path.join(tmpdir, f"{os.path.splitext(src)[0]}{defs[0][-1] if defs else ''}.o")
             cmd = [HIPCC, *FLAGS, *defs, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
             if verbose:

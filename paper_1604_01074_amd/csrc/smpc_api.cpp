@@ -343,11 +343,41 @@ void plan_free(smpc_ctx* ctx, Plan* p) {
   ctx->release(p->items);
   ctx->release(p->td64);
   ctx->release(p->td32);
+  ctx->release(p->tdmix);
   ctx->release(p->done);
   if (p->done_pinned) (void)hipHostFree(p->done_pinned);
   for (hipEvent_t& e : p->done_ev)
     if (e) (void)hipEventDestroy(e);
   delete p;
+}
+
+// The device view of a tree for float32 solve steps on its float64 dual: the
+// float32 node data and work buffers with the float64 dual slots.
+TreeDev<float, double> mixed_view(smpc_tree* t) {
+  const TreeDev<float>& f = t->b32.view;
+  TreeDev<float, double> m{};
+  for (int k = 0; k < 3; ++k) m.y[k] = (double*)t->b64.y[k].ptr;
+  m.beta = f.beta;
+  m.uhat = f.uhat;
+  m.e = f.e;
+  m.pi = f.pi;
+  m.scale = f.scale;
+  m.p = f.p;
+  m.du = f.du;
+  m.z = f.z;
+  m.ctopQ = f.ctopQ;
+  m.ctopR = f.ctopR;
+  m.cstat = f.cstat;
+  m.chains = f.chains;
+  m.st = f.st;
+  m.cnt = f.cnt;
+  m.leaves = f.leaves;
+  m.path_off = f.path_off;
+  m.path = f.path;
+  m.n_chains = f.n_chains;
+  m.n_leaves = f.n_leaves;
+  m.M = f.M;
+  return m;
 }
 
 // Build the launch plan of a set of trees: the leaf chains of all trees
@@ -372,18 +402,25 @@ int plan_build(smpc_ctx* ctx, const std::vector<smpc_tree*>& trees, bool need32,
   if (rc < 0) { plan_free(ctx, p); return rc; }
   std::vector<TreeDev<double>> t64;
   std::vector<TreeDev<float>> t32;
+  std::vector<TreeDev<float, double>> tmix;
   for (smpc_tree* t : trees) {
     t64.push_back(t->b64.view);
-    if (need32) t32.push_back(t->b32.view);
+    if (need32) {
+      t32.push_back(t->b32.view);
+      tmix.push_back(mixed_view(t));
+    }
   }
   rc = ctx->alloc(p->td64, sizeof(TreeDev<double>) * t64.size());
   if (rc >= 0 && need32) rc = ctx->alloc(p->td32, sizeof(TreeDev<float>) * t32.size());
+  if (rc >= 0 && need32) rc = ctx->alloc(p->tdmix, sizeof(TreeDev<float, double>) * tmix.size());
   if (rc < 0) { plan_free(ctx, p); return rc; }
   hipStream_t s = ctx->stream;
   hipError_t e = hipSuccess;
   if (!items.empty()) e = hipMemcpyAsync(p->items.ptr, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(p->td64.ptr, t64.data(), sizeof(TreeDev<double>) * t64.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && need32) e = hipMemcpyAsync(p->td32.ptr, t32.data(), sizeof(TreeDev<float>) * t32.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && need32)
+    e = hipMemcpyAsync(p->tdmix.ptr, tmix.data(), sizeof(TreeDev<float, double>) * tmix.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemsetAsync(p->done.ptr, 0, sizeof(int32_t) * trees.size(), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -394,34 +431,33 @@ int plan_build(smpc_ctx* ctx, const std::vector<smpc_tree*>& trees, bool need32,
   p->has32 = need32;
   p->chunk[0][0] = Chunks<double>::bwd[0];
   p->chunk[0][1] = Chunks<double>::fwd[0];
-  p->chunk[1][0] = Chunks<float>::bwd[0];
-  p->chunk[1][1] = Chunks<float>::fwd[0];
+  p->chunk[1][0] = p->chunk[2][0] = Chunks<float>::bwd[0];
+  p->chunk[1][1] = p->chunk[2][1] = Chunks<float>::fwd[0];
   *out = p;
   return SMPC_OK;
 }
 
-template <typename T>
-const TreeDev<T>* plan_td(Plan* p);
-template <>
-const TreeDev<double>* plan_td<double>(Plan* p) { return (const TreeDev<double>*)p->td64.ptr; }
-template <>
-const TreeDev<float>* plan_td<float>(Plan* p) { return (const TreeDev<float>*)p->td32.ptr; }
+// The plan's device tree table for a (solve-step, dual) precision pair.
+template <typename T, typename Y = T>
+const TreeDev<T, Y>* plan_td(Plan* p) {
+  if constexpr (sizeof(T) == 8) return (const TreeDev<T, Y>*)p->td64.ptr;
+  if constexpr (sizeof(Y) == 8) return (const TreeDev<T, Y>*)p->tdmix.ptr;
+  return (const TreeDev<T, Y>*)p->td32.ptr;
+}
 
-// Index of a precision in the per-plan chunk tables: 0 float64, 1 float32.
-template <typename T>
+// Index of a precision pair in the per-plan tables: 0 float64, 1 float32,
+// 2 float32 solve steps on a float64 dual.
+template <typename T, typename Y = T>
 constexpr int pix() {
-  return sizeof(T) == 4 ? 1 : 0;
+  return sizeof(T) == 8 ? 0 : (sizeof(Y) == 8 ? 2 : 1);
 }
 
-template <typename T>
-const char* kname(int which);
-template <>
-const char* kname<double>(int which) {
-  return which == 0 ? "backward_f64" : (which == 1 ? "forward_f64" : "iter_f64");
-}
-template <>
-const char* kname<float>(int which) {
-  return which == 0 ? "backward_f32" : (which == 1 ? "forward_f32" : "iter_f32");
+template <typename T, typename Y = T>
+const char* kname(int which) {
+  static const char* names[3][3] = {{"backward_f64", "forward_f64", "iter_f64"},
+                                    {"backward_f32", "forward_f32", "iter_f32"},
+                                    {"backward_mix", "forward_mix", "iter_mix"}};
+  return names[pix<T, Y>()][which];
 }
 
 // Enqueue one iteration of `mode` for every tree of the plan: the backward
@@ -429,40 +465,40 @@ const char* kname<float>(int which) {
 // end of iteration -- or, for fused APG iterations, one launch that runs the
 // forward rollout of this iteration and the backward sweep of the next (the
 // caller has run the backward of the first one, see ensure_backward).
-template <typename T>
+template <typename T, typename Y = T>
 int enqueue_iteration(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode) {
   const SysDev<T>& sv = sysbuf<T>(sys).view;
-  const TreeDev<T>* td = plan_td<T>(p);
+  const TreeDev<T, Y>* td = plan_td<T, Y>(p);
   const WorkItem* items = (const WorkItem*)p->items.ptr;
   hipStream_t s = ctx->stream;
-  const int* ch = p->chunk[pix<T>()];
+  const int* ch = p->chunk[pix<T, Y>()];
   if (mode == kModeAPG && p->fused) {
     // forward of this iteration and backward of the next in one launch
-    HIP_TRY(timed(ctx, kname<T>(2), [&] {
-      return launch_iter<T>(sv, td, items, p->n_items, ctx->ctab, ch[0], ch[1], (int32_t*)p->done.ptr, s);
+    HIP_TRY(timed(ctx, kname<T, Y>(2), [&] {
+      return launch_iter<T, Y>(sv, td, items, p->n_items, ctx->ctab, ch[0], ch[1], (int32_t*)p->done.ptr, s);
     }));
     return SMPC_OK;
   }
-  HIP_TRY(timed(ctx, kname<T>(0),
-                [&] { return launch_backward<T>(sv, td, items, p->n_items, ctx->ctab, mode, ch[0], s); }));
-  HIP_TRY(timed(ctx, kname<T>(1), [&] {
-    return launch_forward<T>(sv, td, items, p->n_items, ctx->ctab, mode, ch[1], (int32_t*)p->done.ptr, s);
+  HIP_TRY(timed(ctx, kname<T, Y>(0),
+                [&] { return launch_backward<T, Y>(sv, td, items, p->n_items, ctx->ctab, mode, ch[0], s); }));
+  HIP_TRY(timed(ctx, kname<T, Y>(1), [&] {
+    return launch_forward<T, Y>(sv, td, items, p->n_items, ctx->ctab, mode, ch[1], (int32_t*)p->done.ptr, s);
   }));
-  p->bwd_ready[pix<T>()] = false;  // the next iteration starts with its backward
+  p->bwd_ready[pix<T, Y>()] = false;  // the next iteration starts with its backward
   return SMPC_OK;
 }
 
 // Before fused APG iterations: the backward of every tree's current
 // iteration (one backward launch, outside any captured graph).
-template <typename T>
+template <typename T, typename Y = T>
 int ensure_backward(smpc_ctx* ctx, smpc_sys* sys, Plan* p) {
-  if (!p->fused || p->bwd_ready[pix<T>()]) return SMPC_OK;
+  if (!p->fused || p->bwd_ready[pix<T, Y>()]) return SMPC_OK;
   const SysDev<T>& sv = sysbuf<T>(sys).view;
-  HIP_TRY(timed(ctx, kname<T>(0), [&] {
-    return launch_backward<T>(sv, plan_td<T>(p), (const WorkItem*)p->items.ptr, p->n_items, ctx->ctab, kModeAPG,
-                              p->chunk[pix<T>()][0], ctx->stream);
+  HIP_TRY(timed(ctx, kname<T, Y>(0), [&] {
+    return launch_backward<T, Y>(sv, plan_td<T, Y>(p), (const WorkItem*)p->items.ptr, p->n_items, ctx->ctab,
+                                 kModeAPG, p->chunk[pix<T, Y>()][0], ctx->stream);
   }));
-  p->bwd_ready[pix<T>()] = true;
+  p->bwd_ready[pix<T, Y>()] = true;
   return SMPC_OK;
 }
 
@@ -470,24 +506,24 @@ int ensure_backward(smpc_ctx* ctx, smpc_sys* sys, Plan* p) {
 // hipGraph per (precision, mode, iters, chunk lengths) and replayed: the kernels take every
 // per-iteration quantity from the device-side tree state, so one graph serves
 // every block of a solve.
-template <typename T>
+template <typename T, typename Y = T>
 int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
-  if (mode == kModeAPG) SMPC_TRY(ensure_backward<T>(ctx, sys, p));
+  if (mode == kModeAPG) SMPC_TRY((ensure_backward<T, Y>(ctx, sys, p)));
   if (ctx->profiling) {
-    for (int k = 0; k < iters; ++k) SMPC_TRY(enqueue_iteration<T>(ctx, sys, p, mode));
+    for (int k = 0; k < iters; ++k) SMPC_TRY((enqueue_iteration<T, Y>(ctx, sys, p, mode)));
     return SMPC_OK;
   }
   if (p->graphs_ctab_gen != ctx->ctab_gen) {
     plan_drop_graphs(p);
     p->graphs_ctab_gen = ctx->ctab_gen;
   }
-  const int* ch = p->chunk[pix<T>()];
-  const auto key = std::make_tuple((int)sizeof(T), mode, iters, ch[0], ch[1], (int)(mode == kModeAPG && p->fused));
+  const int* ch = p->chunk[pix<T, Y>()];
+  const auto key = std::make_tuple(pix<T, Y>(), mode, iters, ch[0], ch[1], (int)(mode == kModeAPG && p->fused));
   auto found = p->graphs.find(key);
   if (found == p->graphs.end()) {
     HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
     int rc = SMPC_OK;
-    for (int k = 0; k < iters && rc >= 0; ++k) rc = enqueue_iteration<T>(ctx, sys, p, mode);
+    for (int k = 0; k < iters && rc >= 0; ++k) rc = enqueue_iteration<T, Y>(ctx, sys, p, mode);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
     if (rc < 0) {
@@ -502,7 +538,7 @@ int run_block(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int mode, int iters) {
     found = p->graphs.emplace(key, exec).first;
   }
   HIP_TRY(hipGraphLaunch(found->second, ctx->stream));
-  if (!(mode == kModeAPG && p->fused)) p->bwd_ready[pix<T>()] = false;
+  if (!(mode == kModeAPG && p->fused)) p->bwd_ready[pix<T, Y>()] = false;
   return SMPC_OK;
 }
 
@@ -551,9 +587,10 @@ int wait_done(Plan* p, int slot) {
 // shortest block.  The blocks are iterations of the running solve (the chunk
 // length does not change the iterates).  Consumes up to 3 x pairs blocks of
 // `rounds`; leaves the plan untuned when every tree stops first.
-template <typename T>
+template <typename T, typename Y = T>
 int tune_chunks(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int iters, int max_rounds, int& rounds) {
-  int* ch = p->chunk[pix<T>()];
+  constexpr int K = pix<T, Y>();
+  int* ch = p->chunk[K];
   hipEvent_t ev[2] = {nullptr, nullptr};
   HIP_TRY(hipEventCreate(&ev[0]));
   hipError_t e = hipEventCreate(&ev[1]);
@@ -577,7 +614,7 @@ int tune_chunks(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int iters, int max_rounds
         }
         const bool timed_block = rep > 0;
         if (timed_block) e = hipEventRecord(ev[0], ctx->stream);
-        if (e == hipSuccess) rc = run_block<T>(ctx, sys, p, kModeAPG, iters);
+        if (e == hipSuccess) rc = run_block<T, Y>(ctx, sys, p, kModeAPG, iters);
         if (rc >= 0 && timed_block && e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
         if (rc >= 0 && e == hipSuccess) rc = read_done(ctx, p);
         if (rc >= 0 && timed_block && e == hipSuccess) {
@@ -603,21 +640,21 @@ int tune_chunks(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int iters, int max_rounds
   ch[0] = best_b;
   ch[1] = best_f;
   if (complete) {
-    p->tuned[pix<T>()] = true;
-    sys->tuned_chunk[pix<T>()][0] = best_b;
-    sys->tuned_chunk[pix<T>()][1] = best_f;
-    sys->has_tuned[pix<T>()] = true;
+    p->tuned[K] = true;
+    sys->tuned_chunk[K][0] = best_b;
+    sys->tuned_chunk[K][1] = best_f;
+    sys->has_tuned[K] = true;
   }
   return SMPC_OK;
 }
 
 // Run APG iterations until every tree of the plan is done (after tuning the
 // chunk lengths first when `tune` is set and the plan has no tuned pair).
-template <typename T>
+template <typename T, typename Y = T>
 int run_until_done(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int check_every, int max_rounds, bool tune) {
   int round = 0;
   std::fill(p->done_host.begin(), p->done_host.end(), 0);
-  if (tune && !p->tuned[pix<T>()]) SMPC_TRY(tune_chunks<T>(ctx, sys, p, check_every, max_rounds, round));
+  if (tune && !p->tuned[pix<T, Y>()]) SMPC_TRY((tune_chunks<T, Y>(ctx, sys, p, check_every, max_rounds, round)));
   if (plan_all_done(p)) return SMPC_OK;
   if (round >= max_rounds) return set_error(SMPC_EDEVICE, "iteration driver did not terminate");
   // Blocks run one ahead of the host's read of the stop flags: the flags
@@ -628,11 +665,11 @@ int run_until_done(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int check_every, int m
   // ordered before whatever the caller enqueues next.
   SMPC_TRY(ensure_done_slots(p));
   int slot = 0;
-  SMPC_TRY(run_block<T>(ctx, sys, p, kModeAPG, check_every));
+  SMPC_TRY((run_block<T, Y>(ctx, sys, p, kModeAPG, check_every)));
   SMPC_TRY(copy_done(ctx, p, slot));
   for (++round;; ++round) {
     const bool more = round < max_rounds;
-    if (more) SMPC_TRY(run_block<T>(ctx, sys, p, kModeAPG, check_every));
+    if (more) SMPC_TRY((run_block<T, Y>(ctx, sys, p, kModeAPG, check_every)));
     SMPC_TRY(wait_done(p, slot));  // the flags behind the previous block
     if (plan_all_done(p)) return SMPC_OK;
     if (!more) break;
@@ -784,6 +821,8 @@ int check_opts(const smpc_solve_opts* o) {
   if (o->warm_start < 0 || o->warm_start > 2) return set_error(SMPC_EINVAL, "warm_start must be 0, 1 or 2");
   if (o->warm_start == 2 && !o->y0) return set_error(SMPC_EINVAL, "warm_start 2 needs y0");
   if (o->tune != 0 && o->tune != 1) return set_error(SMPC_EINVAL, "tune must be 0 or 1");
+  if (o->dual64 != 0 && o->dual64 != 1) return set_error(SMPC_EINVAL, "dual64 must be 0 or 1");
+  if (o->gap != 0 && o->gap != 1) return set_error(SMPC_EINVAL, "gap must be 0 or 1");
   for (int w = 0; w < 2; ++w) {
     if (o->chunk32[w] != 0 && !(w == 0 ? chunk_listed(Chunks<float>::bwd, o->chunk32[w])
                                        : chunk_listed(Chunks<float>::fwd, o->chunk32[w])))
@@ -801,8 +840,12 @@ int check_opts(const smpc_solve_opts* o) {
 // arithmetic for a tree)
 
 int stall_limit32(const smpc_solve_opts* o) {
-  // a fixed iteration count (tol = 0) is never cut short
-  return o->tol <= 0.0 || o->stall_checks < 0 ? 0 : (o->stall_checks == 0 ? 100 : o->stall_checks);
+  // a fixed iteration count (tol = 0) is never cut short; on a float64 dual
+  // the float32 phase has no storage floor, so the rule applies only when
+  // asked for explicitly
+  if (o->tol <= 0.0 || o->stall_checks < 0) return 0;
+  if (o->precision == 32 && o->dual64) return o->stall_checks;
+  return o->stall_checks == 0 ? 100 : o->stall_checks;
 }
 
 int init_tree_state(smpc_tree* t, const smpc_solve_opts* o, int iter, int max_iter, double tol, int stall_limit) {
@@ -829,6 +872,7 @@ SolvePhases phases(const smpc_solve_opts* o) {
   ph.max32 = o->max_iter - ph.polish;
   ph.run32 = use32 && ph.max32 > 0;
   ph.run64 = !use32 || ph.polish > 0;
+  ph.mixed = ph.run32 && o->dual64;
   return ph;
 }
 
@@ -841,10 +885,10 @@ int tree_begin(smpc_tree* t, const double* p, const double* q, const smpc_solve_
   if (ph.run32) SMPC_TRY(upload_root<float>(t, p));
   SMPC_TRY(upload_q(t, q));
   if (o->warm_start == 1) {
-    if (ph.run32) SMPC_TRY(start_from_resident<float>(t));
+    if (ph.run32 && !ph.mixed) SMPC_TRY(start_from_resident<float>(t));
     else SMPC_TRY(start_from_resident<double>(t));
     t->shift_ready = false;
-  } else if (ph.run32) {
+  } else if (ph.run32 && !ph.mixed) {
     SMPC_TRY(upload_dual_start<float>(t, y0, yp0));
   } else {
     SMPC_TRY(upload_dual_start<double>(t, y0, yp0));
@@ -860,9 +904,10 @@ int tree_to_fp64(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int sta
   smpc_ctx* ctx = t->sys->ctx;
   const SolvePhases ph = phases(o);
   const int D = 2 * t->sys->nx + t->sys->nu;
-  for (int s = 0; s < 3; ++s)
-    HIP_TRY(launch_widen<float>((const float*)t->b32.y[s].ptr, (double*)t->b64.y[s].ptr, (size_t)t->M * D,
-                                ctx->stream));
+  if (!ph.mixed)  // (a float64 dual is already in place)
+    for (int s = 0; s < 3; ++s)
+      HIP_TRY(launch_widen<float>((const float*)t->b32.y[s].ptr, (double*)t->b64.y[s].ptr, (size_t)t->M * D,
+                                  ctx->stream));
   if (status32 == -9) {
     SMPC_TRY(init_tree_state(t, o, fp32_iters, fp32_iters, 0.0, 0));
     TreeState h;
@@ -884,7 +929,8 @@ int tree_result(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int stat
   SMPC_TRY(read_state(t, &h));
   // the final dual y^{nu+1} stays resident for a shifted warm start
   t->res_slot = h.iters_done % 3;
-  t->res_prec = ph.run64 ? 64 : 32;
+  t->res_prec = (ph.run64 || ph.mixed) ? 64 : 32;
+  t->res_z32 = !ph.run64;
   t->obj_valid = false;
   if (!r) return SMPC_OK;
   r->iterations = h.iters_done;
@@ -896,38 +942,37 @@ int tree_result(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int stat
   else if (ph.run32 && status32 != 2) status = status32 == 0 ? SMPC_OK : SMPC_MAX_ITER;
   else status = h.status == 0 ? SMPC_OK : SMPC_MAX_ITER;
   r->status = status;
-  if (ph.run64) {
-    SMPC_TRY(download_primal<double>(t, r->x, r->u, r->u0));
-    if (r->y) SMPC_TRY(download_dual<double>(t, h.iters_done % 3, r->y));
-  } else {
-    SMPC_TRY(download_primal<float>(t, r->x, r->u, r->u0));
-    if (r->y) SMPC_TRY(download_dual<float>(t, h.iters_done % 3, r->y));
-  }
+  if (ph.run64) SMPC_TRY(download_primal<double>(t, r->x, r->u, r->u0));
+  else SMPC_TRY(download_primal<float>(t, r->x, r->u, r->u0));
+  if (r->y && t->res_prec == 64) SMPC_TRY(download_dual<double>(t, h.iters_done % 3, r->y));
+  else if (r->y) SMPC_TRY(download_dual<float>(t, h.iters_done % 3, r->y));
   return SMPC_OK;
 }
 
-int run_block_prec(smpc_ctx* ctx, smpc_sys* sys, Plan* p, bool fp32, int iters, bool eager) {
-  if (eager) {
-    if (fp32) SMPC_TRY(ensure_backward<float>(ctx, sys, p));
-    else SMPC_TRY(ensure_backward<double>(ctx, sys, p));
-    for (int k = 0; k < iters; ++k) {
-      if (fp32) SMPC_TRY(enqueue_iteration<float>(ctx, sys, p, kModeAPG));
-      else SMPC_TRY(enqueue_iteration<double>(ctx, sys, p, kModeAPG));
-    }
-    return SMPC_OK;
-  }
-  return fp32 ? run_block<float>(ctx, sys, p, kModeAPG, iters) : run_block<double>(ctx, sys, p, kModeAPG, iters);
+template <typename T, typename Y>
+int run_block_eager(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int iters, bool eager) {
+  if (!eager) return run_block<T, Y>(ctx, sys, p, kModeAPG, iters);
+  SMPC_TRY((ensure_backward<T, Y>(ctx, sys, p)));
+  for (int k = 0; k < iters; ++k) SMPC_TRY((enqueue_iteration<T, Y>(ctx, sys, p, kModeAPG)));
+  return SMPC_OK;
+}
+
+int run_block_prec(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int prec, int iters, bool eager) {
+  if (prec == kPrec32) return run_block_eager<float, float>(ctx, sys, p, iters, eager);
+  if (prec == kPrecMix) return run_block_eager<float, double>(ctx, sys, p, iters, eager);
+  return run_block_eager<double, double>(ctx, sys, p, iters, eager);
 }
 
 // Chunk lengths for the options' precisions: explicit entries, else -- with
 // tune and from_sys -- the system's tuned pair, else the default; with tune
 // and without from_sys a pair already marked tuned is kept.
-void choose_chunks(const smpc_sys* sys, const smpc_solve_opts* o, bool from_sys, int (&chunk)[2][2],
-                   bool (&tuned)[2]) {
-  const int* given[2] = {o->chunk64, o->chunk32};
-  const int defaults[2][2] = {{Chunks<double>::bwd[0], Chunks<double>::fwd[0]},
+void choose_chunks(const smpc_sys* sys, const smpc_solve_opts* o, bool from_sys, int (&chunk)[3][2],
+                   bool (&tuned)[3]) {
+  const int* given[3] = {o->chunk64, o->chunk32, o->chunk32};
+  const int defaults[3][2] = {{Chunks<double>::bwd[0], Chunks<double>::fwd[0]},
+                              {Chunks<float>::bwd[0], Chunks<float>::fwd[0]},
                               {Chunks<float>::bwd[0], Chunks<float>::fwd[0]}};
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 3; ++k) {
     const bool explicit_pair = given[k][0] != 0 || given[k][1] != 0;
     if (explicit_pair) {
       for (int w = 0; w < 2; ++w) chunk[k][w] = given[k][w] ? given[k][w] : defaults[k][w];
@@ -941,11 +986,11 @@ void choose_chunks(const smpc_sys* sys, const smpc_solve_opts* o, bool from_sys,
   }
 }
 
-void result_chunks(const int (&chunk)[2][2], const smpc_solve_opts* o, smpc_result* r) {
+void result_chunks(const int (&chunk)[3][2], const smpc_solve_opts* o, smpc_result* r) {
   const SolvePhases ph = phases(o);
   for (int w = 0; w < 2; ++w) {
-    r->chunk32[w] = ph.run32 ? chunk[1][w] : 0;
-    r->chunk64[w] = ph.run64 ? chunk[0][w] : 0;
+    r->chunk32[w] = ph.run32 ? chunk[ph.mixed ? kPrecMix : kPrec32][w] : 0;
+    r->chunk64[w] = ph.run64 ? chunk[kPrec64][w] : 0;
   }
 }
 
@@ -1079,11 +1124,12 @@ int tree_objective(smpc_tree* t, double* part, double* out_dev, smpc_objective* 
   if (!t->plan) SMPC_TRY(ensure_single_plan(t, false));
   TreeBuffers<double>& b = t->b64;
   if (t->res_prec == 32) {
-    // a solve that ended in float32: its iterates, widened (exactly)
+    // a solve that ended in float32: its dual iterates, widened (exactly)
     for (int k = 0; k < 3; ++k)
       HIP_TRY(launch_widen<float>((const float*)t->b32.y[k].ptr, (double*)b.y[k].ptr, (size_t)M * D, ctx->stream));
-    HIP_TRY(launch_widen<float>((const float*)t->b32.z.ptr, (double*)b.z.ptr, (size_t)M * (nx + nu), ctx->stream));
   }
+  if (t->res_z32)  // and its last primal iterate
+    HIP_TRY(launch_widen<float>((const float*)t->b32.z.ptr, (double*)b.z.ptr, (size_t)M * (nx + nu), ctx->stream));
   const int sl = t->res_slot;
   ObjDev o{};
   o.z = (const double*)b.z.ptr;
@@ -1130,7 +1176,7 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
   const SolvePhases ph = phases(o);
   choose_chunks(sys, o, false, plan->chunk, plan->tuned);
   plan->fused = !o->unfused;
-  plan->bwd_ready[0] = plan->bwd_ready[1] = false;  // every tree starts over
+  plan->bwd_ready[0] = plan->bwd_ready[1] = plan->bwd_ready[2] = false;  // every tree starts over
   // tuning takes at most 3 blocks per chunk pair (they are iterations too)
   const int max_rounds = o->max_iter / o->check_every + 3 + 3 * 4;
   std::vector<int> fp32_iters(n, 0), status32(n, 0);
@@ -1143,7 +1189,8 @@ int solve_plan(Plan* plan, const double* const* p, const double* const* q, const
     off += (size_t)t->M * D;
   }
   if (ph.run32) {
-    SMPC_TRY(run_until_done<float>(ctx, sys, plan, o->check_every, max_rounds, o->tune != 0));
+    if (ph.mixed) SMPC_TRY((run_until_done<float, double>(ctx, sys, plan, o->check_every, max_rounds, o->tune != 0)));
+    else SMPC_TRY((run_until_done<float, float>(ctx, sys, plan, o->check_every, max_rounds, o->tune != 0)));
     for (int k = 0; k < n; ++k) {
       TreeState h;
       SMPC_TRY(read_state(plan->trees[k], &h));

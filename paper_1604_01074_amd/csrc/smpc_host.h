@@ -113,9 +113,10 @@ struct smpc_sys {
   bool has32 = false;
   int n_trees = 0;
   // chunk lengths {backward, forward} chosen by the last tuned solve, per
-  // precision ([0] float64, [1] float32); used by servers with tune 1
-  int tuned_chunk[2][2] = {{0, 0}, {0, 0}};
-  bool has_tuned[2] = {false, false};
+  // precision ([0] float64, [1] float32, [2] float32 solve steps on a
+  // float64 dual); used by servers with tune 1
+  int tuned_chunk[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  bool has_tuned[3] = {false, false, false};
 };
 
 template <typename T>
@@ -156,9 +157,11 @@ struct smpc_tree {
   smpc_objective obj_cache{};
   struct Plan* plan = nullptr;  // single-tree launch plan
   // resident dual of the last solve (slot of y^{nu+1} and its precision;
-  // -1 when no solve has left one) and a pending warm-start shift
+  // -1 when no solve has left one), whether its last primal iterate is in
+  // the float32 buffers, and a pending warm-start shift
   int res_slot = -1;
   int res_prec = 0;
+  bool res_z32 = false;
   bool shift_ready = false;
   smpc::DevBuf shift_src, shift_f;  // per internal node: source node, 3 factors
 };
@@ -167,7 +170,7 @@ struct smpc_tree {
 struct Plan {
   std::vector<smpc_tree*> trees;
   int n_items = 0;  // leaf chains of all trees
-  smpc::DevBuf items, td64, td32, done;
+  smpc::DevBuf items, td64, td32, tdmix, done;  // tdmix: float32 data, float64 dual
   std::vector<int32_t> done_host;
   // two pinned host copies of the stop flags and the events behind them
   // (made on the solve driver's first use): it reads one block's flags while
@@ -177,14 +180,14 @@ struct Plan {
   bool has32 = false;
   // chunk lengths {backward, forward} in use per precision ([0] float64,
   // [1] float32) and whether they were chosen by timing
-  int chunk[2][2] = {{0, 0}, {0, 0}};
-  bool tuned[2] = {false, false};
+  int chunk[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  bool tuned[3] = {false, false, false};
   // APG iterations as one fused launch each (forward nu + backward nu + 1);
   // bwd_ready: the backward of every tree's current iteration is done (set
   // by a backward launch or a fused launch, cleared whenever a tree of the
   // plan restarts or another mode runs on it)
   bool fused = true;
-  bool bwd_ready[2] = {false, false};
+  bool bwd_ready[3] = {false, false, false};
   // instantiated graphs of `iters` iterations, keyed by (element size, mode,
   // iters, backward chunk, forward chunk)
   std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
@@ -193,10 +196,16 @@ struct Plan {
 
 namespace smpc {
 // smpc_api.cpp: plans and the per-tree solve steps (shared with the server)
+// The phases of a solve: run32 -- a first phase with float32 solve steps
+// (mixed: on a float64 dual, else on a float32 dual), run64 -- float64
+// iterations (the whole solve, or the polish / the finish after a stall).
 struct SolvePhases {
   int polish = 0, max32 = 0;
-  bool run32 = false, run64 = false;
+  bool run32 = false, run64 = false, mixed = false;
 };
+// Launch-plan precision of a block of iterations: 0 float64, 1 float32,
+// 2 float32 solve steps on a float64 dual.
+enum { kPrec64 = 0, kPrec32 = 1, kPrecMix = 2 };
 SolvePhases phases(const smpc_solve_opts* o);
 int check_opts(const smpc_solve_opts* o);
 int tree_check_ready(smpc_tree* t, bool need_data);
@@ -208,10 +217,10 @@ int tree_begin(smpc_tree* t, const double* p, const double* q, const smpc_solve_
 int tree_to_fp64(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int status32);
 int tree_result(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int status32, smpc_result* r);
 int read_state(smpc_tree* t, TreeState* h);
-int run_block_prec(smpc_ctx* ctx, smpc_sys* sys, Plan* p, bool fp32, int iters, bool eager);
-void choose_chunks(const smpc_sys* sys, const smpc_solve_opts* o, bool from_sys, int (&chunk)[2][2],
-                   bool (&tuned)[2]);
-void result_chunks(const int (&chunk)[2][2], const smpc_solve_opts* o, smpc_result* r);
+int run_block_prec(smpc_ctx* ctx, smpc_sys* sys, Plan* p, int prec, int iters, bool eager);
+void choose_chunks(const smpc_sys* sys, const smpc_solve_opts* o, bool from_sys, int (&chunk)[3][2],
+                   bool (&tuned)[3]);
+void result_chunks(const int (&chunk)[3][2], const smpc_solve_opts* o, smpc_result* r);
 int read_done(smpc_ctx* ctx, Plan* p);
 int ensure_single_plan(smpc_tree* t, bool need32);
 // Device bytes of a tree's float32 buffers and of a system's float32 copy,

@@ -90,9 +90,11 @@ struct SysDev {
   int32_t pad;
 };
 
-template <typename T>
+// T: precision of the solve step and the node data; Y: precision of the
+// dual iterates (Y = T, or a float32 solve step on a float64 dual).
+template <typename T, typename Y = T>
 struct TreeDev {
-  T* y[3];
+  Y* y[3];
   const T* beta;
   const T* uhat;
   const T* e;
@@ -147,17 +149,19 @@ constexpr bool chunk_listed(const int (&a)[N], int v) {
 // launch_iter per iteration); `done_out[tree]` receives each tree's stop flag
 // at the end of the forward rollout.  `chunk` must be listed in
 // Chunks<T> (hipErrorInvalidValue otherwise).
-template <typename T>
-hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
+// Instantiated for (T, Y) = (double, double), (float, float) and (float,
+// double); the last one for the APG mode only.
+template <typename T, typename Y>
+hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items,
                            int n_items, const double* ctab, int mode, int chunk, hipStream_t s);
-template <typename T>
-hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items,
+template <typename T, typename Y>
+hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items,
                           int n_items, const double* ctab, int mode, int chunk, int32_t* done_out, hipStream_t s);
 // One fused APG iteration (forward of iteration nu, then backward of
 // iteration nu + 1); the launch before the first fused one of a run must be
 // a launch_backward of the APG mode.
-template <typename T>
-hipError_t launch_iter(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, typename Y>
+hipError_t launch_iter(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                        const double* ctab, int bchunk, int fchunk, int32_t* done_out, hipStream_t s);
 template <typename T>
 hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s);

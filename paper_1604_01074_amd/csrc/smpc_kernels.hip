@@ -29,8 +29,9 @@
 // which is Alg. 1 multiplied through by L (du_n = L dv_n, ut_n = L v_n).
 // B and A are applied in sparse form; P is held in registers.
 // The library builds this file once (SMPC_KERNEL_PART undefined, every
-// instantiation) or twice in parallel: part 1 holds the float64 kernels and
-// the mixed-precision helpers, part 2 the float32 kernels.
+// instantiation) or three times in parallel: part 1 holds the float64 kernels
+// and the precision-conversion helpers, part 2 the float32 kernels, part 3
+// the float32 solve steps on a float64 dual.
 #include "smpc_internal.h"
 
 #ifndef SMPC_KERNEL_PART
@@ -41,6 +42,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 namespace smpc {
 
@@ -236,30 +238,34 @@ __device__ __forceinline__ T wave_allsum(T v) {
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
-// Per-workgroup view of one iteration of one tree.
-template <typename T>
+// Per-workgroup view of one iteration of one tree.  T is the precision of
+// the solve step, Y that of the dual iterates: the extrapolation, the prox
+// and the dual update run in Y (Y = T, or float solve steps on a float64
+// dual).
+template <typename T, typename Y>
 struct Iter {
   int it;
-  T c, in_scale, lam, ilam;
+  Y c, lam, ilam;
+  T in_scale;
   bool affine, scaled, write_z;
-  const G<T>* ycur;
-  const G<T>* yprv;
-  G<T>* ynew;
+  const G<Y>* ycur;
+  const G<Y>* yprv;
+  G<Y>* ynew;
 };
 
-template <typename T>
-__device__ __forceinline__ Iter<T> make_iter_at(const TreeDev<T>& td, const G<TreeState>* st, const double* ctab,
-                                                int mode, int it) {
-  Iter<T> x;
+template <typename T, typename Y>
+__device__ __forceinline__ Iter<T, Y> make_iter_at(const TreeDev<T, Y>& td, const G<TreeState>* st,
+                                                   const double* ctab, int mode, int it) {
+  Iter<T, Y> x;
   x.it = it;
-  x.c = T(0);
+  x.c = Y(0);
   x.in_scale = T(1);
-  x.lam = T(1);
-  x.ilam = T(1);
+  x.lam = Y(1);
+  x.ilam = Y(1);
   if (mode == kModeAPG) {
-    x.c = (T)gp(ctab)[x.it];
-    x.lam = (T)st->lambda;
-    x.ilam = T(1) / x.lam;
+    x.c = (Y)gp(ctab)[x.it];
+    x.lam = (Y)st->lambda;
+    x.ilam = Y(1) / x.lam;
   }
   if (mode == kModePower) x.in_scale = (T)st->in_scale;
   x.affine = mode != kModePower;
@@ -272,19 +278,19 @@ __device__ __forceinline__ Iter<T> make_iter_at(const TreeDev<T>& td, const G<Tr
   return x;
 }
 
-template <typename T>
-__device__ __forceinline__ Iter<T> make_iter(const TreeDev<T>& td, const G<TreeState>* st, const double* ctab,
-                                             int mode) {
+template <typename T, typename Y>
+__device__ __forceinline__ Iter<T, Y> make_iter(const TreeDev<T, Y>& td, const G<TreeState>* st, const double* ctab,
+                                                int mode) {
   return make_iter_at(td, st, ctab, mode, (int)st->iter);
 }
 
 // The dual point the solve step is evaluated at: the extrapolated
 // w = y + c (y - y_prev) (APG), the normalised power-iteration vector, or y.
-template <typename T, bool AG = false>
-__device__ __forceinline__ T wpoint(const Iter<T>& x, int mode, uint32_t k) {
+template <typename T, typename Y, bool AG = false>
+__device__ __forceinline__ Y wpoint(const Iter<T, Y>& x, int mode, uint32_t k) {
   // AG: y^nu was written in this launch by another workgroup (an inner node
   // of the fused iteration), so it is read at device scope
-  const T y = AG ? __hip_atomic_load(&x.ycur[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : x.ycur[k];
+  const Y y = AG ? __hip_atomic_load(&x.ycur[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : x.ycur[k];
   if (mode == kModeAPG) return y + x.c * (y - x.yprv[k]);
   if (mode == kModePower) return x.in_scale * y;
   return y;
@@ -306,8 +312,8 @@ namespace {
 // held in registers: wave w owns columns [16 NT w, 16 NT (w + 1)) of every
 // 4-row K step).
 // ---------------------------------------------------------------------------
-template <typename T, int KP, int NXL, int CH, bool AG>
-__device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode, int chain,
+template <typename T, typename Y, int KP, int NXL, int CH, bool AG>
+__device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T, Y>& td, const Iter<T, Y>& x, int mode, int chain,
                           const ChainDesc ch, unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
                           const RowCache<T, kNnzBt>& bt, int& par) {
   constexpr int RS = CH + 1;  // row stride of the transposed rho (bank spread)
@@ -389,7 +395,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
           for (int k = kLoadBatch - 1; k >= 0; --k) {
             const uint32_t n = (uint32_t)(nb + (g + k < C ? g + k : C - 1));
             const T sb = x.scaled ? gp(td.scale)[n * 3 + b] : T(1);
-            xi[k] = sb * wpoint<T, AG>(x, mode, n * D + b * nx + ic);
+            xi[k] = (T)((Y)sb * wpoint<T, Y, AG>(x, mode, n * D + b * nx + ic));
           }
 #pragma unroll
           for (int k = kLoadBatch - 1; k >= 0; --k) {
@@ -449,7 +455,8 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T>
         for (int k = 0; k < kLoadBatch; ++k) {
           const uint32_t n = (uint32_t)(nb + (g + k < C ? g + k : C - 1));
           const T s2 = x.scaled ? gp(td.scale)[n * 3 + 2] : T(1);
-          rv[k] = (x.affine ? gp(td.beta)[n * nu + j] : T(0)) + s2 * wpoint<T, AG>(x, mode, n * D + 2 * nx + j);
+          rv[k] = (x.affine ? gp(td.beta)[n * nu + j] : T(0)) +
+                  (T)((Y)s2 * wpoint<T, Y, AG>(x, mode, n * D + 2 * nx + j));
         }
 #pragma unroll
         for (int k = 0; k < kLoadBatch; ++k)
@@ -582,8 +589,8 @@ __device__ __forceinline__ void bwd_zero_rows(const SysDev<T>& sys, unsigned cha
 // children have all been swept (the workgroup that completes a parent's
 // count sweeps it).  AGP: the ancestors' y^nu was written in this launch by
 // other workgroups and is read at device scope.
-template <typename T, int KP, int NXL, int CH, bool AGP>
-__device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode,
+template <typename T, typename Y, int KP, int NXL, int CH, bool AGP>
+__device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T, Y>& td, const Iter<T, Y>& x, int mode,
                                          int leaf, const ChainDesc leaf_desc, unsigned char* smem_raw,
                                          const T (&preg)[KP / 4 * (KP / 64)], const RowCache<T, kNnzBt>& bt,
                                          int& par, int& s_last) {
@@ -592,9 +599,9 @@ __device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T>&
   ChainDesc ch = leaf_desc;
   while (true) {
     if (AGP && chain != leaf)
-      bwd_chain<T, KP, NXL, CH, true>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par);
+      bwd_chain<T, Y, KP, NXL, CH, true>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par);
     else
-      bwd_chain<T, KP, NXL, CH, false>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par);
+      bwd_chain<T, Y, KP, NXL, CH, false>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par);
     const int parent = ch.parent;
     if (parent < 0) break;  // the root chain is done: the sweep is complete
     // the parent's descriptor is fetched while this chain's stores drain
@@ -617,8 +624,8 @@ __device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T>&
 
 // Persistent: workgroup b takes leaf chains b, b + gridDim.x, ... (longest
 // first), so the register-resident P is loaded once per workgroup.
-template <typename T, int KP, int NXL, int CH, int MODE>
-__global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
+template <typename T, typename Y, int KP, int NXL, int CH, int MODE>
+__global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const TreeDev<T, Y>* __restrict__ trees,
                                                         const WorkItem* __restrict__ items, int n_items,
                                                         const double* __restrict__ ctab, int mode_arg) {
   const int mode = MODE == kModeAny ? mode_arg : MODE;
@@ -632,12 +639,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_backward(SysDev<T> sys, const Tre
   int par = 0;
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const WorkItem wi = items[item];
-    const TreeDev<T>& td = trees[wi.tree];
+    const TreeDev<T, Y>& td = trees[wi.tree];
     const G<TreeState>* st = gp(td.st);
     if (st->done) continue;
-    const Iter<T> x = make_iter(td, st, ctab, mode);
-    bwd_item<T, KP, NXL, CH, false>(sys, td, x, mode, wi.chain, gp(td.chains)[wi.chain], smem_raw, preg, bt, par,
-                                    s_last);
+    const Iter<T, Y> x = make_iter(td, st, ctab, mode);
+    bwd_item<T, Y, KP, NXL, CH, false>(sys, td, x, mode, wi.chain, gp(td.chains)[wi.chain], smem_raw, preg, bt, par,
+                                       s_last);
   }
 }
 
@@ -663,8 +670,8 @@ struct Partials {
 // Store of a dual entry: AG and an inner node (an ancestor chain's node,
 // read later in the same fused launch by the workgroup that sweeps that
 // chain) -> device scope; otherwise a plain store.
-template <typename T, bool AG>
-__device__ __forceinline__ void put_dual(G<T>* p, T v, bool inner) {
+template <typename Y, bool AG>
+__device__ __forceinline__ void put_dual(G<Y>* p, Y v, bool inner) {
   if (AG && inner)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   else
@@ -687,10 +694,10 @@ __device__ __forceinline__ void fold_max(Partials& p, double hz, double t) {
 }
 
 // The extrapolated dual point from explicit arrays (see wpoint).
-template <typename T>
-__device__ __forceinline__ T wpoint2(int mode, T c, T in_scale, const G<T>* __restrict__ yc,
-                                     const G<T>* __restrict__ yp, uint32_t k) {
-  const T y = yc[k];
+template <typename T, typename Y>
+__device__ __forceinline__ Y wpoint2(int mode, Y c, T in_scale, const G<Y>* __restrict__ yc,
+                                     const G<Y>* __restrict__ yp, uint32_t k) {
+  const Y y = yc[k];
   if (mode == kModeAPG) return y + c * (y - yp[k]);
   if (mode == kModePower) return in_scale * y;
   return y;
@@ -710,33 +717,36 @@ __device__ __forceinline__ int32_t chunk_code(int32_t cl, int cc) { return __bui
 // of the psi~ blocks and the dual update.  The arrays are distinct
 // allocations (the three dual slots rotate), so the loads of later nodes may
 // be issued before the stores of earlier ones.
-template <typename T, int UP, int CH, bool AG>
-__device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_t cl, int C, int npath, int j, int nx,
-                                              int nu, int D,
+template <typename T, typename Y, int UP, int CH, bool AG>
+__device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T, Y>& x, int32_t cl, int C, int npath, int j,
+                                              int nx, int nu, int D,
                                               const G<T>* __restrict__ du, const G<T>* __restrict__ uhat,
-                                              const G<T>* __restrict__ yc, const G<T>* __restrict__ yp,
-                                              const G<T>* __restrict__ scale, G<T>* __restrict__ ynew,
+                                              const G<Y>* __restrict__ yc, const G<Y>* __restrict__ yp,
+                                              const G<T>* __restrict__ scale, G<Y>* __restrict__ ynew,
                                               G<T>* __restrict__ z, T* sUp, T& utc, T ulo, T uhi, Partials& pt) {
   constexpr int US = UP;
   const int W = nx + nu;
   // all loads of the chunk first, unconditionally (entries past the chunk's
   // end read a valid node), so that they are in flight together; then the
   // recursion, the prox and the stores
-  T duv[CH], uhv[CH], wv[CH], sv[CH];
+  T duv[CH], uhv[CH], sv[CH];
+  Y wv[CH];
 #pragma unroll
   for (int cc = 0; cc < CH; ++cc) {
     const int32_t code = chunk_code(cl, cc);
     const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
     duv[cc] = du[n * nu + j];
     uhv[cc] = x.affine ? uhat[n * nu + j] : T(0);
-    wv[cc] = mode != kModeSolve ? wpoint2(mode, x.c, x.in_scale, yc, yp, n * D + 2 * nx + j) : T(0);
+    wv[cc] = mode != kModeSolve ? wpoint2<T, Y>(mode, x.c, x.in_scale, yc, yp, n * D + 2 * nx + j) : Y(0);
     sv[cc] = x.scaled ? scale[n * 3 + 2] : T(1);
   }
   if (mode == kModeAPG) {
     // the recursion, the prox and the dual update of every node, branch-free
     // (entries past the chunk's end and nodes owned elsewhere are computed,
-    // never stored, and enter the maxima as zeros); only the stores branch
-    T uv[CH], val[CH];
+    // never stored, and enter the maxima as zeros); only the stores branch.
+    // The prox and the update run in the dual's precision Y.
+    T uv[CH];
+    Y val[CH];
 #pragma unroll
     for (int cc = 0; cc < CH; ++cc) {
       const bool keep = cc < C && chunk_code(cl, cc) < 0;  // wave-uniform
@@ -744,11 +754,11 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_
       sUp[cc * US + j] = utc;  // rows past the chunk's end are never read
       const T u = utc + uhv[cc];
       const T s = sv[cc];
-      const T w = wv[cc];
-      const T a = u + w * (x.ilam / s);  // (w / lambda + s u) / s
-      const T t = clampv(a, ulo, uhi);
+      const Y w = wv[cc];
+      const Y a = (Y)u + w * (x.ilam / (Y)s);  // (w / lambda + s u) / s
+      const Y t = clampv(a, (Y)ulo, (Y)uhi);
       uv[cc] = u;
-      val[cc] = w + x.lam * s * (u - t);
+      val[cc] = w + x.lam * (Y)s * ((Y)u - t);
       fold_max(pt, keep ? (double)u : 0.0, keep ? (double)t : 0.0);
       pin(val[cc]);
     }
@@ -759,7 +769,7 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_
       if (code >= 0) continue;  // wave-uniform: the node is owned elsewhere
       const uint32_t n = (uint32_t)(-1 - code);
       if (x.write_z) z[n * W + nx + j] = uv[cc];
-      put_dual<T, AG>(&ynew[n * D + 2 * nx + j], val[cc], cc < npath);
+      put_dual<Y, AG>(&ynew[n * D + 2 * nx + j], val[cc], cc < npath);
     }
     return;
   }
@@ -776,16 +786,16 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_
         if (x.write_z) z[n * W + nx + j] = u;
         if (mode != kModeSolve) {
           const T s = sv[cc];
-          const T w = wv[cc];
+          const Y w = wv[cc];
           if (mode == kModePower) {
             const T g = -s * u;
-            ynew[n * D + 2 * nx + j] = g;
+            ynew[n * D + 2 * nx + j] = (Y)g;
             pt.s0 += (double)g * (double)g;
             pt.s1 += (double)w * (double)g;
           } else {
-            const T a = u + w * (x.ilam / s);  // (w / lambda + s u) / s
-            const T t = clampv(a, ulo, uhi);
-            ynew[n * D + 2 * nx + j] = w + x.lam * s * (u - t);
+            const Y a = (Y)u + w * (x.ilam / (Y)s);  // (w / lambda + s u) / s
+            const Y t = clampv(a, (Y)ulo, (Y)uhi);
+            ynew[n * D + 2 * nx + j] = w + x.lam * (Y)s * ((Y)u - t);
             fold_max(pt, (double)u, (double)t);
           }
         }
@@ -801,12 +811,12 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T>& x, int32_
 // divisions of different nodes are independent, so they overlap -- and
 // stores the dual update and primal output of the owned nodes.  Every value
 // is computed by the same expression as node by node.
-template <typename T, int NXL, int UP, int CH, bool AG>
-__device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T>& x, int b, int32_t cl,
+template <typename T, typename Y, int NXL, int UP, int CH, bool AG>
+__device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T, Y>& x, int b, int32_t cl,
                                                 int C, int npath,
-                                                const T (&ev)[NXL][CH], const T (&wv)[NXL][CH],
+                                                const T (&ev)[NXL][CH], const Y (&wv)[NXL][CH],
                                                 const RowCache<T, kNnzB> (&brow)[NXL], const T (&bnd)[NXL][2],
-                                                const T* sSP, G<T>* __restrict__ ynew, G<T>* __restrict__ z,
+                                                const T* sSP, G<Y>* __restrict__ ynew, G<T>* __restrict__ z,
                                                 const T* sUp, T* cx, T (&xc)[NXL], Partials& pt) {
   constexpr int US = UP;
   const int lane = threadIdx.x & 63;
@@ -892,7 +902,7 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
         const int i = lane + 64 * r;
         if (i < nx) {
           const T g = -s * xs[r][cc];
-          ynew[n * D + b * nx + i] = g;
+          ynew[n * D + b * nx + i] = (Y)g;
           pt.s0 += (double)g * (double)g;
           pt.s1 += (double)wv[r][cc] * (double)g;
         }
@@ -904,32 +914,34 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
   // (nodes past the chunk's end and nodes owned elsewhere are computed too,
   // never stored, and enter the maxima as zeros, which leaves them
   // unchanged); pin() keeps the compiler from sinking this work into the
-  // per-node store branches below, where it would run node by node
-  T val[NXL][CH];
+  // per-node store branches below, where it would run node by node.  The
+  // prox and the update run in the dual's precision Y.
+  Y val[NXL][CH];
 #pragma unroll
   for (int cc = 0; cc < CH; ++cc) {
     const bool keep = cc < C && chunk_code(cl, cc) < 0;  // wave-uniform
     const T s = sSP[4 * cc + b];
-    const T f = x.ilam / s;
-    T a[NXL], pa[NXL];
-    T dsq = T(0);
+    const Y f = x.ilam / (Y)s;
+    Y a[NXL], pa[NXL];
+    Y dsq = Y(0);
 #pragma unroll
     for (int r = 0; r < NXL; ++r) {
-      a[r] = xs[r][cc] + wv[r][cc] * f;  // (w / lambda + s Hz) / s
-      pa[r] = b == 0 ? (a[r] > bnd[r][0] ? a[r] : bnd[r][0]) : clampv(a[r], bnd[r][0], bnd[r][1]);
-      const T d = lane + 64 * r < nx ? a[r] - pa[r] : T(0);
+      a[r] = (Y)xs[r][cc] + wv[r][cc] * f;  // (w / lambda + s Hz) / s
+      const Y lo = (Y)bnd[r][0], hi = (Y)bnd[r][1];
+      pa[r] = b == 0 ? (a[r] > lo ? a[r] : lo) : clampv(a[r], lo, hi);
+      const Y d = lane + 64 * r < nx ? a[r] - pa[r] : Y(0);
       dsq += d * d;
     }
-    const T del = sqrt(wave_allsum(dsq));
-    const T pi_n = b == 0 && sys.safety_by_prob ? sSP[4 * cc + 3] : T(1);
-    const T cb = b == 0 ? (T)sys.W_x * pi_n : (T)sys.gamma_d;
-    const T tau = cb * x.ilam / (s * s);
-    const T k = del <= tau ? T(1) : tau / del;
+    const Y del = sqrt(wave_allsum(dsq));
+    const Y pi_n = b == 0 && sys.safety_by_prob ? (Y)sSP[4 * cc + 3] : Y(1);
+    const Y cb = b == 0 ? (Y)sys.W_x * pi_n : (Y)sys.gamma_d;
+    const Y tau = cb * x.ilam / ((Y)s * (Y)s);
+    const Y k = del <= tau ? Y(1) : tau / del;
 #pragma unroll
     for (int r = 0; r < NXL; ++r) {
       const bool in = keep && lane + 64 * r < nx;
-      const T t = del <= tau ? pa[r] : a[r] - k * (a[r] - pa[r]);
-      val[r][cc] = wv[r][cc] + x.lam * s * (xs[r][cc] - t);
+      const Y t = del <= tau ? pa[r] : a[r] - k * (a[r] - pa[r]);
+      val[r][cc] = wv[r][cc] + x.lam * (Y)s * ((Y)xs[r][cc] - t);
       fold_max(pt, in ? (double)xs[r][cc] : 0.0, in ? (double)t : 0.0);
       pin(val[r][cc]);
     }
@@ -945,14 +957,14 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
       const int i = lane + 64 * r;
       if (i < nx) {
         if (x.write_z && b == 0) z[n * W + i] = xs[r][cc];
-        put_dual<T, AG>(&ynew[n * D + b * nx + i], val[r][cc], cc < npath);
+        put_dual<Y, AG>(&ynew[n * D + b * nx + i], val[r][cc], cc < npath);
       }
     }
   }
 }
 
-template <typename T, int NXL, int UP, int CH, bool AG>
-__device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>& td, const Iter<T>& x, int mode,
+template <typename T, typename Y, int NXL, int UP, int CH, bool AG>
+__device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T, Y>& td, const Iter<T, Y>& x, int mode,
                           const G<int32_t>* codes, int plen, int first, int len, unsigned char* smem_raw,
                           const RowCache<T, kNnzB> (&brow)[NXL], T (&xc)[NXL], T& utc, const T (&bnd)[NXL][2],
                           const T (&ubnd)[2], int& par, Partials& pt) {
@@ -986,13 +998,14 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
       sSPp[4 * tid + 3] = gp(td.pi)[n];
     }
     if (ju)
-      fwd_psi_chunk<T, UP, CH, AG>(mode, x, cur, C, npath, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur, x.yprv,
-                               gp(td.scale), x.ynew, gp(td.z), sUp, utc, ubnd[0], ubnd[1], pt);
+      fwd_psi_chunk<T, Y, UP, CH, AG>(mode, x, cur, C, npath, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur,
+                                      x.yprv, gp(td.scale), x.ynew, gp(td.z), sUp, utc, ubnd[0], ubnd[1], pt);
     // waves 0, 1: e and the dual point of the wave's block, loaded before the
     // barrier, unconditionally (a node owned elsewhere loads a value it does
     // not use; lanes past nx read component 0)
     const int b = wave;  // 0: sigma~, 1: zeta~
-    T wv[NXL][CH], ev[NXL][CH];
+    T ev[NXL][CH];
+    Y wv[NXL][CH];
     if (wave < 2) {
 #pragma unroll
       for (int r = 0; r < NXL; ++r) {
@@ -1003,15 +1016,15 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
           const int32_t code = chunk_code(cur, cc);
           const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
           ev[r][cc] = x.affine ? gp(td.e)[n * nx + ic] : T(0);
-          wv[r][cc] = mode != kModeSolve ? wpoint(x, mode, n * D + b * nx + ic) : T(0);
+          wv[r][cc] = mode != kModeSolve ? wpoint(x, mode, n * D + b * nx + ic) : Y(0);
         }
         if (NXL > 1) __builtin_amdgcn_sched_barrier(0);  // one state row's loads in flight at a time
       }
     }
     __syncthreads();  // ut of the chunk published
     if (wave < 2)
-      fwd_state_chunk<T, NXL, UP, CH, AG>(sys, mode, x, b, cur, C, npath, ev, wv, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
-                                      sXc + (size_t)wave * nx, xc, pt);
+      fwd_state_chunk<T, Y, NXL, UP, CH, AG>(sys, mode, x, b, cur, C, npath, ev, wv, brow, bnd, sSPp, x.ynew,
+                                             gp(td.z), sUp, sXc + (size_t)wave * nx, xc, pt);
     par ^= 1;
   }
 }
@@ -1019,9 +1032,9 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T>
 // Two workgroups per CU, except with two state rows per lane and long
 // chunks (more than 32 bytes of each per-node array per lane): those need
 // more than 256 registers per lane.
-template <typename T, int NXL, int CH>
+template <typename Y, int NXL, int CH>
 constexpr int fwd_min_blocks() {
-  return (NXL > 1 && CH * sizeof(T) > 32) ? 1 : 2;
+  return (NXL > 1 && CH * sizeof(Y) > 32) ? 1 : 2;
 }
 
 // The forward rollout and prox of one leaf chain (with its root path), its
@@ -1058,9 +1071,9 @@ __device__ __forceinline__ void fwd_sys_loads(const SysDev<T>& sys, FwdSys<T, NX
   f.ubnd[1] = (wave >= 2 && j < nu) ? gp(sys.umax)[j] : T(0);
 }
 
-template <typename T, int NXL, int UP, int CH, bool AG, typename AfterRollout>
-__device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, NXL>& fs, const TreeDev<T>& td,
-                                         const WorkItem wi, G<TreeState>* st, const Iter<T>& x, int mode,
+template <typename T, typename Y, int NXL, int UP, int CH, bool AG, typename AfterRollout>
+__device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, NXL>& fs, const TreeDev<T, Y>& td,
+                                         const WorkItem wi, G<TreeState>* st, const Iter<T, Y>& x, int mode,
                                          unsigned char* smem_raw, int& s_last, int32_t* __restrict__ done_out,
                                          AfterRollout after_rollout) {
   const int tid = threadIdx.x;
@@ -1082,8 +1095,8 @@ __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, N
 
   // the root path (ancestor nodes of this leaf chain, root first), then the
   // chain itself, as one sequence (the work item carries both ranges)
-  fwd_nodes<T, NXL, UP, CH, AG>(sys, td, x, mode, gp(td.path) + wi.p0, wi.plen, wi.first, wi.plen + wi.len, smem_raw,
-                                fs.brow, xc, utc, fs.bnd, fs.ubnd, par, pt);
+  fwd_nodes<T, Y, NXL, UP, CH, AG>(sys, td, x, mode, gp(td.path) + wi.p0, wi.plen, wi.first, wi.plen + wi.len,
+                                   smem_raw, fs.brow, xc, utc, fs.bnd, fs.ubnd, par, pt);
 
   after_rollout();  // the fused iteration issues the next sweep's register loads here
   // partials of this leaf chain
@@ -1201,8 +1214,8 @@ __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, N
 }
 
 
-template <typename T, int NXL, int UP, int CH, int MODE>
-__global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forward(SysDev<T> sys, const TreeDev<T>* __restrict__ trees,
+template <typename T, typename Y, int NXL, int UP, int CH, int MODE>
+__global__ __launch_bounds__(kBlock, (fwd_min_blocks<Y, NXL, CH>())) void k_forward(SysDev<T> sys, const TreeDev<T, Y>* __restrict__ trees,
                                                        const WorkItem* __restrict__ items,
                                                        const double* __restrict__ ctab, int mode_arg,
                                                        int32_t* __restrict__ done_out) {
@@ -1212,14 +1225,14 @@ __global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forw
   FwdSys<T, NXL> fs;
   fwd_sys_loads<T, NXL>(sys, fs);
   const WorkItem wi = items[blockIdx.x];
-  const TreeDev<T>& td = trees[wi.tree];
+  const TreeDev<T, Y>& td = trees[wi.tree];
   G<TreeState>* st = gp(td.st);
   if (st->done) {
     if (threadIdx.x == 0) done_out[wi.tree] = 1;
     return;
   }
-  const Iter<T> x = make_iter(td, st, ctab, mode);
-  fwd_item<T, NXL, UP, CH, false>(sys, fs, td, wi, st, x, mode, smem_raw, s_last, done_out, [] {});
+  const Iter<T, Y> x = make_iter(td, st, ctab, mode);
+  fwd_item<T, Y, NXL, UP, CH, false>(sys, fs, td, wi, st, x, mode, smem_raw, s_last, done_out, [] {});
 }
 
 // One fused APG iteration: the forward rollout of iteration nu for a leaf
@@ -1230,14 +1243,14 @@ __global__ __launch_bounds__(kBlock, (fwd_min_blocks<T, NXL, CH>())) void k_forw
 // iteration nu + 1 for nothing; nothing reads it.
 // The fused kernel holds the backward kernel's registers too: with two
 // state rows per lane and 128-wide float64 P it runs one workgroup per CU.
-template <typename T, int KP, int NXL, int FCH>
+template <typename T, typename Y, int KP, int NXL, int FCH>
 constexpr int iter_min_blocks() {
-  return (fwd_min_blocks<T, NXL, FCH>() == 1 || (NXL > 1 && sizeof(T) == 8 && KP == 128)) ? 1 : 2;
+  return (fwd_min_blocks<Y, NXL, FCH>() == 1 || (NXL > 1 && sizeof(T) == 8 && KP == 128)) ? 1 : 2;
 }
 
-template <typename T, int KP, int NXL, int BCH, int FCH>
-__global__ __launch_bounds__(kBlock, (iter_min_blocks<T, KP, NXL, FCH>())) void k_iter(
-    SysDev<T> sys, const TreeDev<T>* __restrict__ trees, const WorkItem* __restrict__ items,
+template <typename T, typename Y, int KP, int NXL, int BCH, int FCH>
+__global__ __launch_bounds__(kBlock, (iter_min_blocks<T, Y, KP, NXL, FCH>())) void k_iter(
+    SysDev<T> sys, const TreeDev<T, Y>* __restrict__ trees, const WorkItem* __restrict__ items,
     const double* __restrict__ ctab, int32_t* __restrict__ done_out) {
   constexpr int NT = KP / 64, KS = KP / 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1245,21 +1258,21 @@ __global__ __launch_bounds__(kBlock, (iter_min_blocks<T, KP, NXL, FCH>())) void 
   FwdSys<T, NXL> fs;
   fwd_sys_loads<T, NXL>(sys, fs);
   const WorkItem wi = items[blockIdx.x];
-  const TreeDev<T>& td = trees[wi.tree];
+  const TreeDev<T, Y>& td = trees[wi.tree];
   G<TreeState>* st = gp(td.st);
   if (st->done) {
     if (threadIdx.x == 0) done_out[wi.tree] = 1;
     return;
   }
-  const Iter<T> xf = make_iter(td, st, ctab, kModeAPG);
+  const Iter<T, Y> xf = make_iter(td, st, ctab, kModeAPG);
   // P and the B' row of the backward half are loaded while the forward half
   // folds its partials (few registers are live there)
   // (and the next iteration's record and this chain's descriptor)
   T preg[KS * NT];
   RowCache<T, kNnzBt> bt;
-  Iter<T> xb;
+  Iter<T, Y> xb;
   ChainDesc leaf_desc;
-  fwd_item<T, NXL, KP, FCH, true>(sys, fs, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out, [&] {
+  fwd_item<T, Y, NXL, KP, FCH, true>(sys, fs, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out, [&] {
     bwd_load_regs<T, KP>(sys, preg, bt);
     xb = make_iter_at(td, st, ctab, kModeAPG, xf.it + 1);
     leaf_desc = gp(td.chains)[wi.chain];
@@ -1267,7 +1280,7 @@ __global__ __launch_bounds__(kBlock, (iter_min_blocks<T, KP, NXL, FCH>())) void 
   __syncthreads();  // the LDS now holds the backward layout
   bwd_zero_rows<T, KP, NXL, BCH>(sys, smem_raw);
   int par = 0;
-  bwd_item<T, KP, NXL, BCH, true>(sys, td, xb, kModeAPG, wi.chain, leaf_desc, smem_raw, preg, bt, par, s_last);
+  bwd_item<T, Y, KP, NXL, BCH, true>(sys, td, xb, kModeAPG, wi.chain, leaf_desc, smem_raw, preg, bt, par, s_last);
 }
 
 template <typename T>
@@ -1332,33 +1345,39 @@ int resident_blocks(K kernel, size_t lds) {
 // fixed; the power iteration and the solve step share one with the mode a
 // run-time argument and the default chunk length (the chunk length never
 // changes the result).
-template <typename T, int KP, int NXL, int CH, int MODE>
-hipError_t launch_backward_ch(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, typename Y, int KP, int NXL, int CH, int MODE>
+hipError_t launch_backward_ch(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                               const double* ctab, int mode, hipStream_t s) {
   const size_t lds = lds_bytes_backward(sys.nx, sys.nu, sizeof(T), CH);
-  hipError_t e = allow_lds(k_backward<T, KP, NXL, CH, MODE>, lds);
+  hipError_t e = allow_lds(k_backward<T, Y, KP, NXL, CH, MODE>, lds);
   if (e != hipSuccess) return e;
-  const int res = resident_blocks(k_backward<T, KP, NXL, CH, MODE>, lds);
+  const int res = resident_blocks(k_backward<T, Y, KP, NXL, CH, MODE>, lds);
   if (res <= 0) return hipErrorInvalidValue;
   const int grid = std::min(n_items, res);
-  hipLaunchKernelGGL((k_backward<T, KP, NXL, CH, MODE>), dim3(grid), dim3(kBlock), lds, s, sys, trees, items,
+  hipLaunchKernelGGL((k_backward<T, Y, KP, NXL, CH, MODE>), dim3(grid), dim3(kBlock), lds, s, sys, trees, items,
                      n_items, ctab, mode);
   return hipGetLastError();
 }
 
-template <typename T, int KP, int NXL>
-hipError_t launch_backward_kp(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+// A float32 solve step on a float64 dual exists for the APG iteration only.
+template <typename T, int KP, int NXL, typename Y>
+hipError_t launch_backward_kp(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                               const double* ctab, int mode, int chunk, hipStream_t s) {
-  if (mode != kModeAPG)
-    return launch_backward_ch<T, KP, NXL, Chunks<T>::bwd[0], kModeAny>(sys, trees, items, n_items, ctab, mode, s);
-  if (chunk == 16) return launch_backward_ch<T, KP, NXL, 16, kModeAPG>(sys, trees, items, n_items, ctab, mode, s);
+  if (mode != kModeAPG) {
+    if constexpr (std::is_same<T, Y>::value)
+      return launch_backward_ch<T, Y, KP, NXL, Chunks<T>::bwd[0], kModeAny>(sys, trees, items, n_items, ctab, mode,
+                                                                            s);
+    return hipErrorInvalidValue;
+  }
+  if (chunk == 16) return launch_backward_ch<T, Y, KP, NXL, 16, kModeAPG>(sys, trees, items, n_items, ctab, mode, s);
   if constexpr (chunk_listed(Chunks<T>::bwd, 32))
-    if (chunk == 32) return launch_backward_ch<T, KP, NXL, 32, kModeAPG>(sys, trees, items, n_items, ctab, mode, s);
+    if (chunk == 32)
+      return launch_backward_ch<T, Y, KP, NXL, 32, kModeAPG>(sys, trees, items, n_items, ctab, mode, s);
   return hipErrorInvalidValue;
 }
 
-template <typename T>
-hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, typename Y>
+hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                            const double* ctab, int mode, int chunk, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (sys.nx > 128 || sys.nu > 128 || !chunk_listed(Chunks<T>::bwd, chunk)) return hipErrorInvalidValue;
@@ -1370,36 +1389,39 @@ hipError_t launch_backward(const SysDev<T>& sys, const TreeDev<T>* trees, const 
             : launch_backward_kp<T, 128, 2>(sys, trees, items, n_items, ctab, mode, chunk, s);
 }
 
-template <typename T, int NXL, int UP, int CH, int MODE>
-hipError_t launch_forward_ch(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, typename Y, int NXL, int UP, int CH, int MODE>
+hipError_t launch_forward_ch(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                              const double* ctab, int mode, int32_t* done_out, hipStream_t s) {
   const size_t lds = lds_bytes_forward(sys.nx, sys.nu, sizeof(T), CH);
-  hipError_t e = allow_lds(k_forward<T, NXL, UP, CH, MODE>, lds);
+  hipError_t e = allow_lds(k_forward<T, Y, NXL, UP, CH, MODE>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_forward<T, NXL, UP, CH, MODE>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items,
+  hipLaunchKernelGGL((k_forward<T, Y, NXL, UP, CH, MODE>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items,
                      ctab, mode, done_out);
   return hipGetLastError();
 }
 
-template <typename T, int NXL, int UP>
-hipError_t launch_forward_t(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, int NXL, int UP, typename Y>
+hipError_t launch_forward_t(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                             const double* ctab, int mode, int chunk, int32_t* done_out, hipStream_t s) {
-  if (mode != kModeAPG)
-    return launch_forward_ch<T, NXL, UP, Chunks<T>::fwd[0], kModeAny>(sys, trees, items, n_items, ctab, mode,
-                                                                       done_out, s);
+  if (mode != kModeAPG) {
+    if constexpr (std::is_same<T, Y>::value)
+      return launch_forward_ch<T, Y, NXL, UP, Chunks<T>::fwd[0], kModeAny>(sys, trees, items, n_items, ctab, mode,
+                                                                           done_out, s);
+    return hipErrorInvalidValue;
+  }
   if (chunk == 8)
-    return launch_forward_ch<T, NXL, UP, 8, kModeAPG>(sys, trees, items, n_items, ctab, mode, done_out, s);
+    return launch_forward_ch<T, Y, NXL, UP, 8, kModeAPG>(sys, trees, items, n_items, ctab, mode, done_out, s);
   if constexpr (chunk_listed(Chunks<T>::fwd, 16))
     if (chunk == 16)
-      return launch_forward_ch<T, NXL, UP, 16, kModeAPG>(sys, trees, items, n_items, ctab, mode, done_out, s);
+      return launch_forward_ch<T, Y, NXL, UP, 16, kModeAPG>(sys, trees, items, n_items, ctab, mode, done_out, s);
   if constexpr (chunk_listed(Chunks<T>::fwd, 4))
     if (chunk == 4)
-      return launch_forward_ch<T, NXL, UP, 4, kModeAPG>(sys, trees, items, n_items, ctab, mode, done_out, s);
+      return launch_forward_ch<T, Y, NXL, UP, 4, kModeAPG>(sys, trees, items, n_items, ctab, mode, done_out, s);
   return hipErrorInvalidValue;
 }
 
-template <typename T>
-hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, typename Y>
+hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                           const double* ctab, int mode, int chunk, int32_t* done_out, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (sys.nu > 128 || sys.nx > 128 || !chunk_listed(Chunks<T>::fwd, chunk)) return hipErrorInvalidValue;
@@ -1410,31 +1432,31 @@ hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T>* trees, const W
             : launch_forward_t<T, 2, 128>(sys, trees, items, n_items, ctab, mode, chunk, done_out, s);
 }
 
-template <typename T, int KP, int NXL, int BCH, int FCH>
-hipError_t launch_iter_ch(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, typename Y, int KP, int NXL, int BCH, int FCH>
+hipError_t launch_iter_ch(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                           const double* ctab, int32_t* done_out, hipStream_t s) {
   const size_t lds = std::max(lds_bytes_forward(sys.nx, sys.nu, sizeof(T), FCH),
                               lds_bytes_backward(sys.nx, sys.nu, sizeof(T), BCH));
-  hipError_t e = allow_lds(k_iter<T, KP, NXL, BCH, FCH>, lds);
+  hipError_t e = allow_lds(k_iter<T, Y, KP, NXL, BCH, FCH>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_iter<T, KP, NXL, BCH, FCH>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab,
+  hipLaunchKernelGGL((k_iter<T, Y, KP, NXL, BCH, FCH>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab,
                      done_out);
   return hipGetLastError();
 }
 
-template <typename T, int KP, int NXL, int BCH>
-hipError_t launch_iter_b(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, int KP, int NXL, int BCH, typename Y>
+hipError_t launch_iter_b(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                          const double* ctab, int fchunk, int32_t* done_out, hipStream_t s) {
-  if (fchunk == 8) return launch_iter_ch<T, KP, NXL, BCH, 8>(sys, trees, items, n_items, ctab, done_out, s);
+  if (fchunk == 8) return launch_iter_ch<T, Y, KP, NXL, BCH, 8>(sys, trees, items, n_items, ctab, done_out, s);
   if constexpr (chunk_listed(Chunks<T>::fwd, 16))
-    if (fchunk == 16) return launch_iter_ch<T, KP, NXL, BCH, 16>(sys, trees, items, n_items, ctab, done_out, s);
+    if (fchunk == 16) return launch_iter_ch<T, Y, KP, NXL, BCH, 16>(sys, trees, items, n_items, ctab, done_out, s);
   if constexpr (chunk_listed(Chunks<T>::fwd, 4))
-    if (fchunk == 4) return launch_iter_ch<T, KP, NXL, BCH, 4>(sys, trees, items, n_items, ctab, done_out, s);
+    if (fchunk == 4) return launch_iter_ch<T, Y, KP, NXL, BCH, 4>(sys, trees, items, n_items, ctab, done_out, s);
   return hipErrorInvalidValue;
 }
 
-template <typename T, int KP, int NXL>
-hipError_t launch_iter_kp(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, int KP, int NXL, typename Y>
+hipError_t launch_iter_kp(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                           const double* ctab, int bchunk, int fchunk, int32_t* done_out, hipStream_t s) {
   if (bchunk == 16) return launch_iter_b<T, KP, NXL, 16>(sys, trees, items, n_items, ctab, fchunk, done_out, s);
   if constexpr (chunk_listed(Chunks<T>::bwd, 32))
@@ -1442,8 +1464,8 @@ hipError_t launch_iter_kp(const SysDev<T>& sys, const TreeDev<T>* trees, const W
   return hipErrorInvalidValue;
 }
 
-template <typename T>
-hipError_t launch_iter(const SysDev<T>& sys, const TreeDev<T>* trees, const WorkItem* items, int n_items,
+template <typename T, typename Y>
+hipError_t launch_iter(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                        const double* ctab, int bchunk, int fchunk, int32_t* done_out, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   if (sys.nx > 128 || sys.nu > 128 || !chunk_listed(Chunks<T>::bwd, bchunk) || !chunk_listed(Chunks<T>::fwd, fchunk))
@@ -1456,13 +1478,34 @@ hipError_t launch_iter(const SysDev<T>& sys, const TreeDev<T>* trees, const Work
             : launch_iter_kp<T, 128, 2>(sys, trees, items, n_items, ctab, bchunk, fchunk, done_out, s);
 }
 
-#if SMPC_KERNEL_PART != 2
-template hipError_t launch_iter<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
-                                        const double*, int, int, int32_t*, hipStream_t);
+// Part 1: float64; part 2: float32; part 3: float32 solve steps on a float64
+// dual (0: all of them).
+#if SMPC_KERNEL_PART == 0 || SMPC_KERNEL_PART == 1
+template hipError_t launch_iter<double, double>(const SysDev<double>&, const TreeDev<double, double>*,
+                                                const WorkItem*, int, const double*, int, int, int32_t*, hipStream_t);
+template hipError_t launch_backward<double, double>(const SysDev<double>&, const TreeDev<double, double>*,
+                                                    const WorkItem*, int, const double*, int, int, hipStream_t);
+template hipError_t launch_forward<double, double>(const SysDev<double>&, const TreeDev<double, double>*,
+                                                   const WorkItem*, int, const double*, int, int, int32_t*,
+                                                   hipStream_t);
 #endif
-#if SMPC_KERNEL_PART != 1
-template hipError_t launch_iter<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
-                                       const double*, int, int, int32_t*, hipStream_t);
+#if SMPC_KERNEL_PART == 0 || SMPC_KERNEL_PART == 2
+template hipError_t launch_iter<float, float>(const SysDev<float>&, const TreeDev<float, float>*, const WorkItem*,
+                                              int, const double*, int, int, int32_t*, hipStream_t);
+template hipError_t launch_backward<float, float>(const SysDev<float>&, const TreeDev<float, float>*,
+                                                  const WorkItem*, int, const double*, int, int, hipStream_t);
+template hipError_t launch_forward<float, float>(const SysDev<float>&, const TreeDev<float, float>*,
+                                                 const WorkItem*, int, const double*, int, int, int32_t*,
+                                                 hipStream_t);
+#endif
+#if SMPC_KERNEL_PART == 0 || SMPC_KERNEL_PART == 3
+template hipError_t launch_iter<float, double>(const SysDev<float>&, const TreeDev<float, double>*, const WorkItem*,
+                                               int, const double*, int, int, int32_t*, hipStream_t);
+template hipError_t launch_backward<float, double>(const SysDev<float>&, const TreeDev<float, double>*,
+                                                   const WorkItem*, int, const double*, int, int, hipStream_t);
+template hipError_t launch_forward<float, double>(const SysDev<float>&, const TreeDev<float, double>*,
+                                                  const WorkItem*, int, const double*, int, int, int32_t*,
+                                                  hipStream_t);
 #endif
 
 template <typename T>
@@ -1473,18 +1516,8 @@ hipError_t launch_widen(const T* src, double* dst, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-#if SMPC_KERNEL_PART != 2
-template hipError_t launch_backward<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
-                                            const double*, int, int, hipStream_t);
-template hipError_t launch_forward<double>(const SysDev<double>&, const TreeDev<double>*, const WorkItem*, int,
-                                           const double*, int, int, int32_t*, hipStream_t);
+#if SMPC_KERNEL_PART == 0 || SMPC_KERNEL_PART == 1
 template hipError_t launch_widen<float>(const float*, double*, size_t, hipStream_t);
-#endif
-#if SMPC_KERNEL_PART != 1
-template hipError_t launch_backward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
-                                           const double*, int, int, hipStream_t);
-template hipError_t launch_forward<float>(const SysDev<float>&, const TreeDev<float>*, const WorkItem*, int,
-                                          const double*, int, int, int32_t*, hipStream_t);
 #endif
 
 template <typename Ts, typename Td>
@@ -1497,7 +1530,7 @@ hipError_t launch_shift(const Ts* src, Td* dst0, Td* dst2, const int32_t* src_no
   return hipGetLastError();
 }
 
-#if SMPC_KERNEL_PART != 2
+#if SMPC_KERNEL_PART == 0 || SMPC_KERNEL_PART == 1
 template hipError_t launch_shift<double, double>(const double*, double*, double*, const int32_t*, const double*,
                                                  int, int, int, hipStream_t);
 template hipError_t launch_shift<double, float>(const double*, float*, float*, const int32_t*, const double*, int,

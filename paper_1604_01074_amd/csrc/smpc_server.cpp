@@ -56,7 +56,9 @@ struct smpc_server {
   smpc_sys* sys = nullptr;
   smpc_solve_opts o{};
   int max_active = 0;
-  int chunk[2][2] = {{0, 0}, {0, 0}};  // chunk lengths of its launch groups ([0] float64, [1] float32)
+  // chunk lengths of its launch groups ([0] float64, [1] float32, [2] float32
+  // solve steps on a float64 dual)
+  int chunk[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   bool restarted[2] = {false, false};  // a tree of launch group g (0 float32, 1 float64) started over
   std::thread worker;
   std::mutex mu;
@@ -155,7 +157,7 @@ int sync_group(smpc_server* S, int g) {
   S->members[g] = want;
   if (want.empty()) return SMPC_OK;
   SMPC_TRY(plan_build(ctx, want, g == 0, &S->group[g]));
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 3; ++k)
     for (int w = 0; w < 2; ++w) S->group[g]->chunk[k][w] = S->chunk[k][w];
   S->group[g]->fused = !S->o.unfused;
   return SMPC_OK;
@@ -215,10 +217,11 @@ void worker_main(smpc_server* S) {
       rc = sync_group(S, g);
       if (rc >= 0 && S->group[g] && S->restarted[g]) {
         // a tree of the group started over: its current backward is not done
-        S->group[g]->bwd_ready[0] = S->group[g]->bwd_ready[1] = false;
+        S->group[g]->bwd_ready[0] = S->group[g]->bwd_ready[1] = S->group[g]->bwd_ready[2] = false;
       }
       S->restarted[g] = false;
-      if (rc >= 0 && S->group[g]) rc = run_block_prec(ctx, S->sys, S->group[g], g == 0, S->o.check_every, true);
+      const int prec = g == 1 ? kPrec64 : (ph.mixed ? kPrecMix : kPrec32);
+      if (rc >= 0 && S->group[g]) rc = run_block_prec(ctx, S->sys, S->group[g], prec, S->o.check_every, true);
     }
     for (int g = 0; g < 2 && rc >= 0; ++g)
       if (S->group[g]) rc = read_done(ctx, S->group[g]);
@@ -307,7 +310,7 @@ int smpc_server_create(smpc_sys* sys, const smpc_server_opts* opts, smpc_server*
   S->o = opts->solve;
   S->o.y0 = S->o.y_prev0 = nullptr;
   S->max_active = opts->max_active;
-  bool tuned[2] = {false, false};
+  bool tuned[3] = {false, false, false};
   choose_chunks(sys, &S->o, true, S->chunk, tuned);
   try {
     S->worker = std::thread(worker_main, S);

@@ -34,7 +34,7 @@ EXPORTED = [
     "smpc_solve", "smpc_solve_batch", "smpc_shift_warm_start", "smpc_solve_step",
     "smpc_ctx_set_profiling", "smpc_ctx_kernel_stats", "smpc_ctx_reset_stats",
     "smpc_server_create", "smpc_server_submit", "smpc_server_poll", "smpc_server_cancel", "smpc_server_destroy",
-    "smpc_chunk_lengths",
+    "smpc_chunk_lengths", "smpc_plant_step", "smpc_closed_loop_kpi",
 ]
 
 
@@ -83,7 +83,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
                 ("precision", C.c_int), ("polish_iters", C.c_int), ("warm_start", C.c_int),
                 ("y0", _dp), ("y_prev0", _dp), ("stall_checks", C.c_int), ("tune", C.c_int),
-                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2), ("unfused", C.c_int), ("gap", C.c_int)]
+                ("chunk32", C.c_int * 2), ("chunk64", C.c_int * 2), ("unfused", C.c_int), ("gap", C.c_int),
+                ("dual64", C.c_int)]
 
 
 class Result(C.Structure):
@@ -96,6 +97,10 @@ class Result(C.Structure):
 class Objective(C.Structure):
     _fields_ = [("cost", C.c_double), ("primal", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
                 ("dual_violation", C.c_double)]
+
+
+class Kpi(C.Structure):
+    _fields_ = [("E", C.c_double), ("dU", C.c_double), ("S", C.c_double), ("R", C.c_double)]
 
 
 class ServerOpts(C.Structure):
@@ -136,6 +141,8 @@ _sig = {
     "smpc_server_cancel": [_vp, C.c_uint64],
     "smpc_server_destroy": [_vp],
     "smpc_chunk_lengths": [C.c_int, C.c_int, _ip, C.c_int, _ip],
+    "smpc_plant_step": [_vp, _dp, _dp, _dp, _dp],
+    "smpc_closed_loop_kpi": [_vp, C.c_int, _dp, _dp, _dp, _dp, C.POINTER(Kpi)],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -289,14 +296,14 @@ def _pair(v):
 
 
 def _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks=0, resident=False,
-          tune=0, chunk32=None, chunk64=None, unfused=False, gap=False):
+          tune=0, chunk32=None, chunk64=None, unfused=False, gap=False, dual64=False):
     keep = [None if y0 is None else _f64(y0), None if y_prev0 is None else _f64(y_prev0)]
     if resident and y0 is not None:
         raise ValueError("a resident warm start and y0 exclude each other")
     warm = 1 if resident else (2 if y0 is not None else 0)
     o = SolveOpts(float(tol), int(max_iter), int(check_every), int(precision), int(polish_iters),
                   warm, _ptr(keep[0]), _ptr(keep[1]), int(stall_checks), int(tune), _pair(chunk32),
-                  _pair(chunk64), int(bool(unfused)), int(bool(gap)))
+                  _pair(chunk64), int(bool(unfused)), int(bool(gap)), int(bool(dual64)))
     return o, keep
 
 
@@ -321,13 +328,13 @@ def _finish(r: Result, out: dict) -> dict:
 
 def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precision=64, polish_iters=0,
                y0=None, y_prev0=None, want_x=True, want_y=True, stall_checks=0, resident=False, tune=0,
-               chunk32=None, chunk64=None, unfused=False, gap=False) -> dict:
+               chunk32=None, chunk64=None, unfused=False, gap=False, dual64=False) -> dict:
     """``dims = (M, nx, nu)``.  Returns a dict with u0, x, u, y, iterations,
     fp32_iterations, r_primal, hz_t_max, status, chunk32, chunk64, cost, gap
     (the last two with ``gap=True``)."""
     M, nx, nu = dims
     o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident,
-                    tune, chunk32, chunk64, unfused, gap)
+                    tune, chunk32, chunk64, unfused, gap, dual64)
     r, out = _result(M, nx, nu, want_x, want_y)
     pp, qq = _f64(p), _f64(q)
     _check_solve(_lib.smpc_solve(t, _ptr(pp), _ptr(qq), C.byref(o), C.byref(r)))
@@ -337,10 +344,10 @@ def smpc_solve(t, p, q, *, dims, tol=1e-3, max_iter=1000, check_every=10, precis
 def smpc_solve_batch(trees, ps, qs, *, dims_list, tol=1e-3, max_iter=1000, check_every=10, precision=64,
                      polish_iters=0, y0=None, y_prev0=None, want_x=True, want_y=True,
                      stall_checks=0, resident=False, tune=0, chunk32=None, chunk64=None,
-                     unfused=False, gap=False) -> tuple[int, list]:
+                     unfused=False, gap=False, dual64=False) -> tuple[int, list]:
     n = len(trees)
     o, keep = _opts(tol, max_iter, check_every, precision, polish_iters, y0, y_prev0, stall_checks, resident,
-                    tune, chunk32, chunk64, unfused, gap)
+                    tune, chunk32, chunk64, unfused, gap, dual64)
     res = (Result * n)()
     outs = []
     for k, (M, nx, nu) in enumerate(dims_list):
@@ -379,6 +386,25 @@ def smpc_chunk_lengths(precision: int, which: int) -> list:
     return [arr[k] for k in range(n.value)]
 
 
+# ---------------------------------------------------------------- closed loop
+
+def smpc_plant_step(s, x, u, d):
+    xx, uu = _f64(x), _f64(u)
+    dd = None if d is None else _f64(d)
+    out = np.empty_like(xx)
+    _check(_lib.smpc_plant_step(s, _ptr(xx), _ptr(uu), _ptr(dd), _ptr(out)))
+    return out
+
+
+def smpc_closed_loop_kpi(s, u, x, alpha2, u_prev) -> dict:
+    """KPIs of Sec. V-B: u (Hs, nu), x (Hs, nx), alpha2 (Hs, nu) or None."""
+    uu, xx, pp = _f64(u), _f64(x), _f64(u_prev)
+    aa = None if alpha2 is None else _f64(alpha2)
+    k = Kpi()
+    _check(_lib.smpc_closed_loop_kpi(s, int(uu.shape[0]), _ptr(uu), _ptr(xx), _ptr(aa), _ptr(pp), C.byref(k)))
+    return {"E": k.E, "dU": k.dU, "S": k.S, "R": k.R}
+
+
 # ---------------------------------------------------------------- profiling
 
 def smpc_ctx_set_profiling(ctx, enable: bool) -> None:
@@ -400,9 +426,10 @@ def smpc_ctx_reset_stats(ctx) -> None:
 # ---------------------------------------------------------------- serving
 
 def smpc_server_create(sys_handle, *, tol=1e-3, max_iter=1000, check_every=10, precision=32, polish_iters=20,
-                       stall_checks=0, max_active=0, tune=0, chunk32=None, chunk64=None, unfused=False):
+                       stall_checks=0, max_active=0, tune=0, chunk32=None, chunk64=None, unfused=False,
+                       dual64=False):
     o, _ = _opts(tol, max_iter, check_every, precision, polish_iters, None, None, stall_checks, False, tune,
-                 chunk32, chunk64, unfused)
+                 chunk32, chunk64, unfused, False, dual64)
     so = ServerOpts(o, int(max_active))
     h = _vp()
     _check(_lib.smpc_server_create(sys_handle, C.byref(so), C.byref(h)))
