@@ -139,8 +139,11 @@ int smpc_tree_get_data(smpc_tree* tree, double* uhat, double* e, double* beta);
  *   scaling), which needed about half the iterations of 1 on the
  *   Barcelona-shaped trees.
  * scale: optional M*3 caller-given scaling (overrides precond when non-NULL).
- * power_iters: power-iteration steps on the device for the largest
- *   eigenvalue L of the (scaled) dual Hessian (default 200 when <= 0).
+ * power_iters: the least number of power-iteration steps on the device for
+ *   the largest eigenvalue L of the (scaled) dual Hessian (default 200 when
+ *   <= 0); the iteration then goes on, 10 steps at a time, until its
+ *   Rayleigh quotient (which approaches L from below) changes by less than
+ *   1e-5 relative over 10 steps, for at most 10 x power_iters steps in all.
  * lambda_override > 0 skips the power iteration and uses that step size.
  * The step used is lambda = 1 / (L * (1 + margin)), margin = 0.02 when L
  * comes from the power iteration.                                            */

@@ -24,13 +24,16 @@ def run(tree, x0, q0, steps, *, warm: bool = False, realized=None, keep_y: bool 
     pumping costs (N, nu) at step k; the realised demand is the root's
     ``d[0]``.  ``realized(k)`` picks the root child the warm start of step
     k + 1 follows (default 0).  Returns the applied inputs ``u`` (Hs, nu),
-    the states ``x`` (Hs, nx) they lead to, per-step iterations, status and
-    wall time, and the KPIs (with ``keep_y`` also each step's final dual
-    ``y``)."""
+    the states ``x`` (Hs, nx) they lead to, per-step iterations, status,
+    primal residual ``||Hz - t||_inf`` and wall time (with ``gap=True`` in
+    ``solve_kw`` also each step's cost and duality gap, the a-posteriori
+    check of Sec. IV-E), and the KPIs (with ``keep_y`` also each step's
+    final dual ``y``)."""
     sysh = tree.system.h
     x = np.asarray(x0, dtype=np.float64).copy()
     q = np.asarray(q0, dtype=np.float64).copy()
     us, xs, its, st, secs, ys = [], [], [], [], [], []
+    res, costs, gaps = [], [], []
     for k, (d, a2) in enumerate(steps):
         t0 = time.perf_counter()
         tree.set_data(d, a2)
@@ -47,11 +50,17 @@ def run(tree, x0, q0, steps, *, warm: bool = False, realized=None, keep_y: bool 
         xs.append(x.copy())
         its.append(r["iterations"])
         st.append(r["status"])
+        res.append(r["hz_t_max"])
+        if solve_kw.get("gap"):
+            costs.append(r["cost"])
+            gaps.append(r["gap"])
         q = u0
     u_arr, x_arr = np.array(us), np.array(xs)
     a2_arr = np.array([np.asarray(a2)[0] for _, a2 in steps])
     kpi = S.smpc_closed_loop_kpi(sysh, u_arr, x_arr, a2_arr, np.asarray(q0, dtype=np.float64))
-    out = {"u": u_arr, "x": x_arr, "iterations": its, "status": st, "seconds": secs, "kpi": kpi}
+    out = {"u": u_arr, "x": x_arr, "iterations": its, "status": st, "hz_t_max": res, "seconds": secs, "kpi": kpi}
+    if gaps:
+        out["cost"], out["gap"] = costs, gaps
     if keep_y:
         out["y"] = ys
     return out

@@ -1771,11 +1771,25 @@ int smpc_factor(smpc_tree* t, const smpc_factor_opts* o) {
   st.lambda = 1.0;
   st.in_scale = 1.0 / std::sqrt(nrm);
   SMPC_TRY(write_state(t, st));
+  // at least `iters` steps; then on until the Rayleigh quotient (which
+  // approaches L from below) changes by less than kPowerTol over a block of
+  // 10 steps, for at most 10 x iters steps in all
   const int iters = o->power_iters > 0 ? o->power_iters : 200;
-  for (int k = 0; k < iters; k += 10) SMPC_TRY(run_block<double>(ctx, s, t->plan, kModePower, std::min(10, iters - k)));
-  SMPC_TRY(read_state(t, &st));
-  if (!(st.lmax_est > 0.0) || !std::isfinite(st.lmax_est))
-    return set_error(SMPC_EDEVICE, "power iteration failed (estimate %g)", st.lmax_est);
+  constexpr double kPowerTol = 1e-5;
+  double prev = 0.0;
+  int k = 0;
+  while (true) {
+    const int n = k < iters ? std::min(10, iters - k) : 10;
+    SMPC_TRY(run_block<double>(ctx, s, t->plan, kModePower, n));
+    k += n;
+    if (k < iters) continue;
+    SMPC_TRY(read_state(t, &st));
+    if (!(st.lmax_est > 0.0) || !std::isfinite(st.lmax_est))
+      return set_error(SMPC_EDEVICE, "power iteration failed (estimate %g)", st.lmax_est);
+    if (std::fabs(st.lmax_est - prev) <= kPowerTol * st.lmax_est || k >= 10 * iters) break;
+    prev = st.lmax_est;
+  }
+  t->power_steps = k;
   t->lmax = st.lmax_est;
   t->lambda = 1.0 / (st.lmax_est * 1.02);
   t->factored = true;

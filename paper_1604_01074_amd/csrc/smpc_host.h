@@ -144,6 +144,7 @@ struct smpc_tree {
   bool factored = false;
   double lambda = 0.0;
   double lmax = 0.0;
+  int power_steps = 0;  // power-iteration steps the last smpc_factor ran
   // device
   TreeBuffers<double> b64;
   TreeBuffers<float> b32;
