@@ -263,6 +263,13 @@ __host__ __device__ inline size_t lds_bytes_backward(int nx, int nu, size_t elem
   return elem * (2 * ch * xs + (size_t)p_stride(nu) * (ch + 1) + 2 * ch + 3 * (size_t)nx);
 }
 
+// LDS per CU on gfx950, and where the forward layout starts when the fused
+// iteration keeps the backward layout beside it (16-byte aligned).
+constexpr size_t kLdsPerCu = 160 * 1024;
+__host__ __device__ inline size_t lds_stash_offset(int nx, int nu, size_t elem, int chunk) {
+  return (lds_bytes_backward(nx, nu, elem, chunk) + 15) & ~(size_t)15;
+}
+
 __host__ __device__ inline size_t lds_bytes_forward(int nx, int nu, size_t elem, int chunk) {
   // ut of two chunks (2 x chunk x padded nu), scales and pi of two chunks,
   // the x carries of waves 0 and 1 (general A), 32 float64 reduction slots

@@ -284,6 +284,30 @@ __device__ __forceinline__ Iter<T, Y> make_iter(const TreeDev<T, Y>& td, const G
   return make_iter_at(td, st, ctab, mode, (int)st->iter);
 }
 
+// The arithmetic that forms the solve step's inputs from the dual iterates,
+// fixed so that every code path gives the same bits: the extrapolation is
+// one fused multiply-add, and the scaled dual point is rounded on its own
+// (never fused into the sum that follows).
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename Y>
+__device__ __forceinline__ Y extrapolate(Y y, Y y_prev, Y c) {
+  return fmadd(c, y - y_prev, y);
+}
+
+template <typename T, typename Y>
+__device__ __forceinline__ T scaled(T s, Y w) {
+#pragma clang fp contract(off)
+  return (T)((Y)s * w);
+}
+
+template <typename T, typename Y>
+__device__ __forceinline__ T beta_plus_scaled(T beta, T s, Y w) {
+#pragma clang fp contract(off)
+  return beta + (T)((Y)s * w);
+}
+
 // The dual point the solve step is evaluated at: the extrapolated
 // w = y + c (y - y_prev) (APG), the normalised power-iteration vector, or y.
 template <typename T, typename Y, bool AG = false>
@@ -291,7 +315,7 @@ __device__ __forceinline__ Y wpoint(const Iter<T, Y>& x, int mode, uint32_t k) {
   // AG: y^nu was written in this launch by another workgroup (an inner node
   // of the fused iteration), so it is read at device scope
   const Y y = AG ? __hip_atomic_load(&x.ycur[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : x.ycur[k];
-  if (mode == kModeAPG) return y + x.c * (y - x.yprv[k]);
+  if (mode == kModeAPG) return extrapolate(y, x.yprv[k], x.c);
   if (mode == kModePower) return x.in_scale * y;
   return y;
 }
@@ -312,10 +336,13 @@ namespace {
 // held in registers: wave w owns columns [16 NT w, 16 NT (w + 1)) of every
 // 4-row K step).
 // ---------------------------------------------------------------------------
+// stashed: the forward half of this launch has left the chain's xi, r and
+// -1/(2 pi) in LDS (a leaf chain of at most CH nodes; see Stash), so the
+// loads are skipped.
 template <typename T, typename Y, int KP, int NXL, int CH, bool AG>
 __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T, Y>& td, const Iter<T, Y>& x, int mode, int chain,
                           const ChainDesc ch, unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
-                          const RowCache<T, kNnzBt>& bt, int& par) {
+                          const RowCache<T, kNnzBt>& bt, int& par, bool stashed) {
   constexpr int RS = CH + 1;  // row stride of the transposed rho (bank spread)
   constexpr int NT = KP / 64, KS = KP / 4, MT = CH / 16;
   constexpr int XS = 64 * NXL;  // row stride of the Q parts (>= nx, a constant)
@@ -374,42 +401,58 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
     const int C = top - k0;
     const int nb = ch.first + k0;  // internal index of the chunk's first node
     T* sIp = sI + par * CH;
-    if (tid < C) sIp[tid] = T(-0.5) / gp(td.pi)[nb + tid];
+    if (!stashed && tid < C) sIp[tid] = T(-0.5) / gp(td.pi)[nb + tid];
     if (wave < 2) {
       // this wave's part of xi_n (block b = wave); with A = I the Q recursion
       // runs along, bottom node first
       const int b = wave;
       T* sQw = sQ + wave * CH * XS;
+      if (stashed) {
+        // the raw xi parts are in place: with A = I the running sum over
+        // them (the general-A recursion below reads them as they are)
+        if (sys.a_identity) {
 #pragma unroll
-      for (int r = 0; r < NXL; ++r) {
-        const int i = lane + 64 * r;
-        const uint32_t ic = (uint32_t)(i < nx ? i : 0);
-#pragma unroll
-        for (int g = CH - kLoadBatch; g >= 0; g -= kLoadBatch) {
-          if (g >= C) continue;  // wave-uniform: the batch lies past the chunk's end
-          // every load of the batch first, unconditionally (nodes past the
-          // chunk's end read its last node, lanes past nx component 0), so
-          // that they are in flight together; then the recursion
-          T xi[kLoadBatch];
-#pragma unroll
-          for (int k = kLoadBatch - 1; k >= 0; --k) {
-            const uint32_t n = (uint32_t)(nb + (g + k < C ? g + k : C - 1));
-            const T sb = x.scaled ? gp(td.scale)[n * 3 + b] : T(1);
-            xi[k] = (T)((Y)sb * wpoint<T, Y, AG>(x, mode, n * D + b * nx + ic));
-          }
-#pragma unroll
-          for (int k = kLoadBatch - 1; k >= 0; --k) {
-            const int cc = g + k;
-            if (cc < C && i < nx) {
-              if (sys.a_identity) {
-                qc[r] += xi[k];
+          for (int r = 0; r < NXL; ++r) {
+            const int i = lane + 64 * r;
+            if (i < nx)
+              for (int cc = C - 1; cc >= 0; --cc) {
+                qc[r] += sQw[cc * XS + i];
                 sQw[cc * XS + i] = qc[r];
-              } else {
-                sQw[cc * XS + i] = xi[k];
+              }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < NXL; ++r) {
+          const int i = lane + 64 * r;
+          const uint32_t ic = (uint32_t)(i < nx ? i : 0);
+#pragma unroll
+          for (int g = CH - kLoadBatch; g >= 0; g -= kLoadBatch) {
+            if (g >= C) continue;  // wave-uniform: the batch lies past the chunk's end
+            // every load of the batch first, unconditionally (nodes past the
+            // chunk's end read its last node, lanes past nx component 0), so
+            // that they are in flight together; then the recursion
+            T xi[kLoadBatch];
+#pragma unroll
+            for (int k = kLoadBatch - 1; k >= 0; --k) {
+              const uint32_t n = (uint32_t)(nb + (g + k < C ? g + k : C - 1));
+              const T sb = x.scaled ? gp(td.scale)[n * 3 + b] : T(1);
+              xi[k] = scaled<T, Y>(sb, wpoint<T, Y, AG>(x, mode, n * D + b * nx + ic));
+            }
+#pragma unroll
+            for (int k = kLoadBatch - 1; k >= 0; --k) {
+              const int cc = g + k;
+              if (cc < C && i < nx) {
+                if (sys.a_identity) {
+                  qc[r] += xi[k];
+                  sQw[cc * XS + i] = qc[r];
+                } else {
+                  sQw[cc * XS + i] = xi[k];
+                }
               }
             }
+            __builtin_amdgcn_sched_barrier(0);
           }
-          __builtin_amdgcn_sched_barrier(0);
         }
       }
       if (!sys.a_identity) {
@@ -444,7 +487,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
         }
       }
     }
-    if (ju) {
+    if (ju && !stashed) {
       // r_n = beta_n + S w_psi, parked in this thread's row of the rho tile;
       // loads batched as above
 #pragma unroll
@@ -455,8 +498,8 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
         for (int k = 0; k < kLoadBatch; ++k) {
           const uint32_t n = (uint32_t)(nb + (g + k < C ? g + k : C - 1));
           const T s2 = x.scaled ? gp(td.scale)[n * 3 + 2] : T(1);
-          rv[k] = (x.affine ? gp(td.beta)[n * nu + j] : T(0)) +
-                  (T)((Y)s2 * wpoint<T, Y, AG>(x, mode, n * D + 2 * nx + j));
+          rv[k] = beta_plus_scaled<T, Y>(x.affine ? gp(td.beta)[n * nu + j] : T(0), s2,
+                                         wpoint<T, Y, AG>(x, mode, n * D + 2 * nx + j));
         }
 #pragma unroll
         for (int k = 0; k < kLoadBatch; ++k)
@@ -466,23 +509,41 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
     }
     __syncthreads();  // Q parts complete
     if (ju) {
-      // rho recursion, bottom node first: r_n + B' Q_n + rho_below
+      // rho recursion, bottom node first: r_n + B' Q_n + rho_below.  The
+      // terms r_n + B' Q_n of a group of nodes are formed first, in one
+      // branch-free block (a group reaching past the chunk's top reads node
+      // 0 again and discards it), so that their LDS reads overlap; then the
+      // running sum.  A lane whose B' row exceeds the register cache sends
+      // the wave through the CSR arrays.
       const T* sQz = sQ + CH * XS;
+      if (!__any(bt.n > kNnzBt)) {
+        constexpr int RG = (sizeof(T) == 8 && NXL > 1) ? 1 : 2;  // as registers allow beside P
+        for (int hi = C; hi > 0; hi -= RG) {
+          T g[RG];
 #pragma unroll
-      for (int cc = CH - 1; cc >= 0; --cc)
-        if (cc < C) {
-          T g = sRt[j * RS + cc];
-          if (bt.n <= kNnzBt) {
+          for (int k = 0; k < RG; ++k) {
+            const int cs = hi - 1 - k >= 0 ? hi - 1 - k : 0;
+            T v = sRt[j * RS + cs];
 #pragma unroll
-            for (int q = 0; q < kNnzBt; ++q) g += bt.w[q] * (sQ[cc * XS + bt.c[q]] + sQz[cc * XS + bt.c[q]]);
-          } else {
-            for (int q = bt.q0; q < bt.q1; ++q)
-              g += gp(sys.bt_v)[q] * (sQ[cc * XS + gp(sys.bt_ci)[q]] + sQz[cc * XS + gp(sys.bt_ci)[q]]);
+            for (int q = 0; q < kNnzBt; ++q) v += bt.w[q] * (sQ[cs * XS + bt.c[q]] + sQz[cs * XS + bt.c[q]]);
+            g[k] = v;
           }
+#pragma unroll
+          for (int k = 0; k < RG; ++k)
+            if (hi - 1 - k >= 0) {  // wave-uniform
+              rc += g[k];
+              sRt[j * RS + hi - 1 - k] = rc;
+            }
+        }
+      } else {
+        for (int cc = C - 1; cc >= 0; --cc) {
+          T g = sRt[j * RS + cc];
+          for (int q = bt.q0; q < bt.q1; ++q)
+            g += gp(sys.bt_v)[q] * (sQ[cc * XS + gp(sys.bt_ci)[q]] + sQz[cc * XS + gp(sys.bt_ci)[q]]);
           rc += g;
           sRt[j * RS + cc] = rc;
-          if (cc % kLoadBatch == 0) __builtin_amdgcn_sched_barrier(0);
         }
+      }
     }
     __syncthreads();  // sRt complete
     if (ch.len <= kValuChain) {
@@ -593,15 +654,16 @@ template <typename T, typename Y, int KP, int NXL, int CH, bool AGP>
 __device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T, Y>& td, const Iter<T, Y>& x, int mode,
                                          int leaf, const ChainDesc leaf_desc, unsigned char* smem_raw,
                                          const T (&preg)[KP / 4 * (KP / 64)], const RowCache<T, kNnzBt>& bt,
-                                         int& par, int& s_last) {
+                                         int& par, int& s_last, bool leaf_stashed = false) {
   const int tid = threadIdx.x;
   int chain = leaf;
   ChainDesc ch = leaf_desc;
   while (true) {
     if (AGP && chain != leaf)
-      bwd_chain<T, Y, KP, NXL, CH, true>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par);
+      bwd_chain<T, Y, KP, NXL, CH, true>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par, false);
     else
-      bwd_chain<T, Y, KP, NXL, CH, false>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par);
+      bwd_chain<T, Y, KP, NXL, CH, false>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par,
+                                          leaf_stashed && chain == leaf);
     const int parent = ch.parent;
     if (parent < 0) break;  // the root chain is done: the sweep is complete
     // the parent's descriptor is fetched while this chain's stores drain
@@ -667,6 +729,23 @@ struct Partials {
   bool nan;           // a NaN met on the way (fmax would drop it)
 };
 
+// The fused iteration's hand-over from the forward rollout to the backward
+// sweep of the same leaf chain: for the chain's own nodes the forward half
+// writes what the next sweep would load -- xi_n = S (w_sigma + w_zeta) per
+// block (raw, before the running sum), r_n = beta_n + S w_psi and
+// -1/(2 pi_n) -- straight into the backward layout in LDS, with w the next
+// iteration's extrapolated point formed from y^{nu+1} just computed and y^nu
+// already in registers (the same expressions, in the same order, as the
+// sweep's loads would give).  q == nullptr: no hand-over.
+template <typename T, typename Y>
+struct Stash {
+  T* q;    // Q parts: block b at q + b * bch * xs, node k of the chain at row k
+  T* r;    // transposed rho tile: r[j * rs + k]
+  T* inv;  // -1/(2 pi) of node k
+  int xs, rs, bch;
+  Y cn;    // the extrapolation coefficient of the next iteration
+};
+
 // Store of a dual entry: AG and an inner node (an ancestor chain's node,
 // read later in the same fused launch by the workgroup that sweeps that
 // chain) -> device scope; otherwise a plain store.
@@ -685,6 +764,16 @@ __device__ __forceinline__ void pin(T& v) {
   asm volatile("" : "+v"(v));
 }
 
+// The prox work of a chunk's nodes is pinned node by node (each node its own
+// scheduling region: an inline asm bounds one) or after the whole chunk (the
+// nodes' independent work overlaps, at the cost of more live registers).
+// Overlap only for short chunks with one state row per lane and T = Y: the
+// other variants would spill or lose a wave per SIMD.
+template <typename T, typename Y, int NXL, int CH>
+constexpr bool pin_per_node() {
+  return sizeof(T) < sizeof(Y) || NXL * CH > 4;
+}
+
 __device__ __forceinline__ void fold_max(Partials& p, double hz, double t) {
   const double r = hz - t;
   p.nan |= (r != r);
@@ -698,7 +787,7 @@ template <typename T, typename Y>
 __device__ __forceinline__ Y wpoint2(int mode, Y c, T in_scale, const G<Y>* __restrict__ yc,
                                      const G<Y>* __restrict__ yp, uint32_t k) {
   const Y y = yc[k];
-  if (mode == kModeAPG) return y + c * (y - yp[k]);
+  if (mode == kModeAPG) return extrapolate(y, yp[k], c);
   if (mode == kModePower) return in_scale * y;
   return y;
 }
@@ -722,24 +811,33 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T, Y>& x, int
                                               int nx, int nu, int D,
                                               const G<T>* __restrict__ du, const G<T>* __restrict__ uhat,
                                               const G<Y>* __restrict__ yc, const G<Y>* __restrict__ yp,
-                                              const G<T>* __restrict__ scale, G<Y>* __restrict__ ynew,
-                                              G<T>* __restrict__ z, T* sUp, T& utc, T ulo, T uhi, Partials& pt) {
+                                              const G<T>* __restrict__ scale, const G<T>* __restrict__ beta,
+                                              G<Y>* __restrict__ ynew, G<T>* __restrict__ z, T* sUp, T& utc, T ulo,
+                                              T uhi, const Stash<T, Y>& sh, Partials& pt) {
   constexpr int US = UP;
   const int W = nx + nu;
+  const bool stash = sh.q != nullptr;
   // all loads of the chunk first, unconditionally (entries past the chunk's
   // end read a valid node), so that they are in flight together; then the
   // recursion, the prox and the stores
-  T duv[CH], uhv[CH], sv[CH];
-  Y wv[CH];
+  T duv[CH], uhv[CH], sv[CH], bv[CH];
+  Y yv[CH], wv[CH];
 #pragma unroll
   for (int cc = 0; cc < CH; ++cc) {
     const int32_t code = chunk_code(cl, cc);
     const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
+    const uint32_t k = n * D + 2 * nx + j;
     duv[cc] = du[n * nu + j];
     uhv[cc] = x.affine ? uhat[n * nu + j] : T(0);
-    wv[cc] = mode != kModeSolve ? wpoint2<T, Y>(mode, x.c, x.in_scale, yc, yp, n * D + 2 * nx + j) : Y(0);
+    yv[cc] = mode != kModeSolve ? yc[k] : Y(0);
+    wv[cc] = mode == kModeAPG ? yp[k] : Y(0);
     sv[cc] = x.scaled ? scale[n * 3 + 2] : T(1);
+    bv[cc] = stash ? beta[n * nu + j] : T(0);
   }
+  // the dual point (see wpoint2)
+#pragma unroll
+  for (int cc = 0; cc < CH; ++cc)
+    wv[cc] = mode == kModeAPG ? extrapolate(yv[cc], wv[cc], x.c) : (mode == kModePower ? x.in_scale * yv[cc] : Y(0));
   if (mode == kModeAPG) {
     // the recursion, the prox and the dual update of every node, branch-free
     // (entries past the chunk's end and nodes owned elsewhere are computed,
@@ -760,7 +858,15 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T, Y>& x, int
       uv[cc] = u;
       val[cc] = w + x.lam * (Y)s * ((Y)u - t);
       fold_max(pt, keep ? (double)u : 0.0, keep ? (double)t : 0.0);
-      pin(val[cc]);
+      if constexpr (pin_per_node<T, Y, 1, CH>()) pin(val[cc]);
+      if (stash && cc >= npath && cc < C) {  // wave-uniform: a node of this chain
+        const Y v = val[cc];
+        sh.r[j * sh.rs + (cc - npath)] = beta_plus_scaled<T, Y>(bv[cc], s, extrapolate(v, yv[cc], sh.cn));
+      }
+    }
+    if constexpr (!pin_per_node<T, Y, 1, CH>()) {
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) pin(val[cc]);
     }
 #pragma unroll
     for (int cc = 0; cc < CH; ++cc) {
@@ -815,6 +921,7 @@ template <typename T, typename Y, int NXL, int UP, int CH, bool AG>
 __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T, Y>& x, int b, int32_t cl,
                                                 int C, int npath,
                                                 const T (&ev)[NXL][CH], const Y (&wv)[NXL][CH],
+                                                const Y (&yv)[NXL][CH], T* stq, int sxs, Y cn,
                                                 const RowCache<T, kNnzB> (&brow)[NXL], const T (&bnd)[NXL][2],
                                                 const T* sSP, G<Y>* __restrict__ ynew, G<T>* __restrict__ z,
                                                 const T* sUp, T* cx, T (&xc)[NXL], Partials& pt) {
@@ -829,13 +936,25 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
     for (int r = 0; r < NXL; ++r) {
       const int i = lane + 64 * r;
       T g[CH];
+      // a lane whose B row exceeds the register cache sends the whole wave
+      // through the CSR arrays; otherwise every LDS read of the chunk is
+      // issued before the products (one basic block, no per-lane branch)
+      if (!__any(brow[r].n > kNnzB)) {
+        T bu[CH][kNnzB];
 #pragma unroll
-      for (int cc = 0; cc < CH; ++cc) {
-        g[cc] = ev[r][cc];
-        if (brow[r].n <= kNnzB) {
+        for (int cc = 0; cc < CH; ++cc)
 #pragma unroll
-          for (int q = 0; q < kNnzB; ++q) g[cc] += brow[r].w[q] * sUp[cc * US + brow[r].c[q]];
-        } else {
+          for (int q = 0; q < kNnzB; ++q) bu[cc][q] = sUp[cc * US + brow[r].c[q]];
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          g[cc] = ev[r][cc];
+#pragma unroll
+          for (int q = 0; q < kNnzB; ++q) g[cc] += brow[r].w[q] * bu[cc][q];
+        }
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          g[cc] = ev[r][cc];
           for (int q = brow[r].q0; q < brow[r].q1; ++q) g[cc] += gp(sys.b_v)[q] * sUp[cc * US + gp(sys.b_ci)[q]];
         }
       }
@@ -943,8 +1062,19 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
       const Y t = del <= tau ? pa[r] : a[r] - k * (a[r] - pa[r]);
       val[r][cc] = wv[r][cc] + x.lam * (Y)s * ((Y)xs[r][cc] - t);
       fold_max(pt, in ? (double)xs[r][cc] : 0.0, in ? (double)t : 0.0);
-      pin(val[r][cc]);
+      if constexpr (pin_per_node<T, Y, NXL, CH>()) pin(val[r][cc]);
+      // a node of this chain: the next sweep's xi_n part of block b
+      if (stq != nullptr && cc >= npath && cc < C && lane + 64 * r < nx) {
+        const Y v = val[r][cc];
+        stq[(cc - npath) * sxs + lane + 64 * r] = scaled<T, Y>(s, extrapolate(v, yv[r][cc], cn));
+      }
     }
+  }
+  if constexpr (!pin_per_node<T, Y, NXL, CH>()) {
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc)
+#pragma unroll
+      for (int r = 0; r < NXL; ++r) pin(val[r][cc]);
   }
 #pragma unroll
   for (int cc = 0; cc < CH; ++cc) {
@@ -963,11 +1093,49 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
   }
 }
 
+// Waves 0 and 1: e and the dual iterates of the wave's block for the nodes of
+// a chunk (entries past the sequence repeat its last node; lanes past nx read
+// component 0).
+template <typename T, typename Y, int NXL, int CH>
+struct StateLoads {
+  T e[NXL][CH];
+  Y y[NXL][CH], yp[NXL][CH];
+};
+
+// Loaded one chunk ahead of their use when two sets fit in registers beside
+// the rest of the rollout (at most 96 bytes per lane each).
+template <typename T, typename Y, int NXL, int CH>
+constexpr bool state_prefetch() {
+  return NXL * CH * (sizeof(T) + 2 * sizeof(Y)) <= 96;
+}
+
+template <typename T, typename Y, int NXL, int CH>
+__device__ __forceinline__ void load_state(const TreeDev<T, Y>& td, const Iter<T, Y>& x, int mode, int nx, int D,
+                                           int b, int32_t cl, StateLoads<T, Y, NXL, CH>& L) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < NXL; ++r) {
+    const int i = lane + 64 * r;
+    const uint32_t ic = (uint32_t)(i < nx ? i : 0);
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) {
+      const int32_t code = chunk_code(cl, cc);
+      const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
+      const uint32_t k = n * D + b * nx + ic;
+      L.e[r][cc] = x.affine ? gp(td.e)[n * nx + ic] : T(0);
+      L.y[r][cc] = mode != kModeSolve ? x.ycur[k] : Y(0);
+      L.yp[r][cc] = mode == kModeAPG ? x.yprv[k] : Y(0);
+    }
+    if (NXL > 1) __builtin_amdgcn_sched_barrier(0);  // one state row's loads in flight at a time
+  }
+}
+
 template <typename T, typename Y, int NXL, int UP, int CH, bool AG>
 __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T, Y>& td, const Iter<T, Y>& x, int mode,
                           const G<int32_t>* codes, int plen, int first, int len, unsigned char* smem_raw,
                           const RowCache<T, kNnzB> (&brow)[NXL], T (&xc)[NXL], T& utc, const T (&bnd)[NXL][2],
-                          const T (&ubnd)[2], int& par, Partials& pt) {
+                          const T (&ubnd)[2], const Stash<T, Y>& sh, int& par, Partials& pt) {
+  constexpr bool PF = state_prefetch<T, Y, NXL, CH>();
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -977,55 +1145,98 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T,
   T* sU = reinterpret_cast<T*>(smem_raw);  // 2 x CH x UP (UP >= nu, a constant)
   T* sSP = sU + 2 * CH * UP;               // 2 x CH x 4: scales and pi of the chunk's nodes
   T* sXc = sSP + 2 * 4 * CH;               // 2 x nx (general A: carries of waves 0, 1)
-
-  // every wave keeps the node codes of the current chunk in a register
-  // (lane k: entry k0 + k; entries past the sequence repeat its last node),
-  // and loads the next chunk's while the current one runs
+  // every wave keeps the node codes of the current and the next chunk in
+  // registers (lane k: entry k0 + k, resp. k0 + CH + k; entries past the
+  // sequence repeat its last node) and loads the codes one chunk further
+  // while the current chunk runs
   const int last = len - 1;
   int32_t cl = node_code(codes, plen, first, lane < last ? lane : last);
-  for (int k0 = 0; k0 < len; k0 += CH) {
+  int32_t cn = node_code(codes, plen, first, CH + lane < last ? CH + lane : last);
+  StateLoads<T, Y, NXL, CH> LA, LB;
+  if (PF && wave < 2) load_state<T, Y, NXL, CH>(td, x, mode, nx, D, wave, cl, LA);
+
+  // one chunk: Lc holds (without prefetch: receives) its state loads, Ln
+  // receives the next chunk's (the loop below alternates the two sets, so
+  // that no register copy waits for loads in flight)
+  auto chunk = [&](int k0, StateLoads<T, Y, NXL, CH>& Lc, StateLoads<T, Y, NXL, CH>& Ln) {
     const int C = len - k0 < CH ? len - k0 : CH;
     const int npath = plen - k0;  // entries cc < npath are ancestor (inner) nodes
     const int32_t cur = cl;
-    if (k0 + CH < len) cl = node_code(codes, plen, first, k0 + CH + lane < last ? k0 + CH + lane : last);
+    const int32_t nxt = cn;
+    if (k0 + 2 * CH < len) cn = node_code(codes, plen, first, k0 + 2 * CH + lane < last ? k0 + 2 * CH + lane : last);
+    cl = nxt;
+    const int b = wave;  // 0: sigma~, 1: zeta~
+    // the dual point of the wave's block (see wpoint)
+    Y wv[NXL][CH];
+    auto dual_point = [&] {
+#pragma unroll
+      for (int r = 0; r < NXL; ++r)
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          const Y y = Lc.y[r][cc];
+          wv[r][cc] = mode == kModeAPG ? extrapolate(y, Lc.yp[r][cc], x.c) : (mode == kModePower ? x.in_scale * y : Y(0));
+        }
+    };
+    if (wave < 2) {
+      if (!PF) {
+        load_state<T, Y, NXL, CH>(td, x, mode, nx, D, b, cur, Lc);
+      } else {
+        // this chunk's loads (issued one chunk ago) are consumed before the
+        // next chunk's are issued: the wait counter counts loads in issue
+        // order, so a first use after the next issue would wait for those too
+        dual_point();
+#pragma unroll
+        for (int r = 0; r < NXL; ++r)
+#pragma unroll
+          for (int cc = 0; cc < CH; ++cc) {
+            pin(wv[r][cc]);
+            pin(Lc.e[r][cc]);
+          }
+        __builtin_amdgcn_sched_barrier(0);
+        if (k0 + CH < len) load_state<T, Y, NXL, CH>(td, x, mode, nx, D, b, nxt, Ln);
+      }
+    }
     T* sUp = sU + par * CH * UP;
     T* sSPp = sSP + par * 4 * CH;
-    if (tid < C) {
-      const int32_t code = cur;  // wave 0: lane tid holds entry k0 + tid
-      const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
-      sSPp[4 * tid] = x.scaled ? gp(td.scale)[n * 3] : T(1);
-      sSPp[4 * tid + 1] = x.scaled ? gp(td.scale)[n * 3 + 1] : T(1);
-      sSPp[4 * tid + 3] = gp(td.pi)[n];
+    // wave 2 stages the scales and pi of the chunk's nodes (lane k: entry
+    // k0 + k) around its own loads, so that waves 0 and 1 never wait for them
+    const bool spl = wave == 2 && lane < C;
+    T sp0 = T(1), sp1 = T(1), sp3 = T(1);
+    if (spl) {
+      const uint32_t n = (uint32_t)(cur < 0 ? -1 - cur : cur);
+      if (x.scaled) {
+        sp0 = gp(td.scale)[n * 3];
+        sp1 = gp(td.scale)[n * 3 + 1];
+      }
+      sp3 = gp(td.pi)[n];
     }
     if (ju)
       fwd_psi_chunk<T, Y, UP, CH, AG>(mode, x, cur, C, npath, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur,
-                                      x.yprv, gp(td.scale), x.ynew, gp(td.z), sUp, utc, ubnd[0], ubnd[1], pt);
-    // waves 0, 1: e and the dual point of the wave's block, loaded before the
-    // barrier, unconditionally (a node owned elsewhere loads a value it does
-    // not use; lanes past nx read component 0)
-    const int b = wave;  // 0: sigma~, 1: zeta~
-    T ev[NXL][CH];
-    Y wv[NXL][CH];
-    if (wave < 2) {
-#pragma unroll
-      for (int r = 0; r < NXL; ++r) {
-        const int i = lane + 64 * r;
-        const uint32_t ic = (uint32_t)(i < nx ? i : 0);
-#pragma unroll
-        for (int cc = 0; cc < CH; ++cc) {
-          const int32_t code = chunk_code(cur, cc);
-          const uint32_t n = (uint32_t)(code < 0 ? -1 - code : code);
-          ev[r][cc] = x.affine ? gp(td.e)[n * nx + ic] : T(0);
-          wv[r][cc] = mode != kModeSolve ? wpoint(x, mode, n * D + b * nx + ic) : Y(0);
-        }
-        if (NXL > 1) __builtin_amdgcn_sched_barrier(0);  // one state row's loads in flight at a time
-      }
+                                      x.yprv, gp(td.scale), gp(td.beta), x.ynew, gp(td.z), sUp, utc, ubnd[0],
+                                      ubnd[1], sh, pt);
+    if (spl) {
+      sSPp[4 * lane] = sp0;
+      sSPp[4 * lane + 1] = sp1;
+      sSPp[4 * lane + 3] = sp3;
+      if (sh.q != nullptr && lane >= npath) sh.inv[lane - npath] = T(-0.5) / sp3;  // a node of this chain
     }
-    __syncthreads();  // ut of the chunk published
-    if (wave < 2)
-      fwd_state_chunk<T, Y, NXL, UP, CH, AG>(sys, mode, x, b, cur, C, npath, ev, wv, brow, bnd, sSPp, x.ynew,
-                                             gp(td.z), sUp, sXc + (size_t)wave * nx, xc, pt);
+    __syncthreads();  // ut and the scales of the chunk published
+    if (wave < 2) {
+      if (!PF) dual_point();
+      fwd_state_chunk<T, Y, NXL, UP, CH, AG>(sys, mode, x, b, cur, C, npath, Lc.e, wv, Lc.y,
+                                             sh.q != nullptr ? sh.q + (size_t)b * sh.bch * sh.xs : nullptr, sh.xs,
+                                             sh.cn, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
+                                             sXc + (size_t)wave * nx, xc, pt);
+    }
     par ^= 1;
+  };
+  if constexpr (PF) {
+    for (int k0 = 0; k0 < len; k0 += 2 * CH) {
+      chunk(k0, LA, LB);
+      if (k0 + CH < len) chunk(k0 + CH, LB, LA);
+    }
+  } else {
+    for (int k0 = 0; k0 < len; k0 += CH) chunk(k0, LA, LA);
   }
 }
 
@@ -1075,7 +1286,7 @@ template <typename T, typename Y, int NXL, int UP, int CH, bool AG, typename Aft
 __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, NXL>& fs, const TreeDev<T, Y>& td,
                                          const WorkItem wi, G<TreeState>* st, const Iter<T, Y>& x, int mode,
                                          unsigned char* smem_raw, int& s_last, int32_t* __restrict__ done_out,
-                                         AfterRollout after_rollout) {
+                                         const Stash<T, Y>& sh, AfterRollout after_rollout) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -1096,7 +1307,7 @@ __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, N
   // the root path (ancestor nodes of this leaf chain, root first), then the
   // chain itself, as one sequence (the work item carries both ranges)
   fwd_nodes<T, Y, NXL, UP, CH, AG>(sys, td, x, mode, gp(td.path) + wi.p0, wi.plen, wi.first, wi.plen + wi.len,
-                                   smem_raw, fs.brow, xc, utc, fs.bnd, fs.ubnd, par, pt);
+                                   smem_raw, fs.brow, xc, utc, fs.bnd, fs.ubnd, sh, par, pt);
 
   after_rollout();  // the fused iteration issues the next sweep's register loads here
   // partials of this leaf chain
@@ -1232,7 +1443,8 @@ __global__ __launch_bounds__(kBlock, (fwd_min_blocks<Y, NXL, CH>())) void k_forw
     return;
   }
   const Iter<T, Y> x = make_iter(td, st, ctab, mode);
-  fwd_item<T, Y, NXL, UP, CH, false>(sys, fs, td, wi, st, x, mode, smem_raw, s_last, done_out, [] {});
+  const Stash<T, Y> none{nullptr, nullptr, nullptr, 0, 0, 0, Y(0)};
+  fwd_item<T, Y, NXL, UP, CH, false>(sys, fs, td, wi, st, x, mode, smem_raw, s_last, done_out, none, [] {});
 }
 
 // One fused APG iteration: the forward rollout of iteration nu for a leaf
@@ -1248,10 +1460,13 @@ constexpr int iter_min_blocks() {
   return (fwd_min_blocks<Y, NXL, FCH>() == 1 || (NXL > 1 && sizeof(T) == 8 && KP == 128)) ? 1 : 2;
 }
 
+// stash_arg: the LDS holds the backward layout and the forward's after it, so
+// that a leaf chain of at most BCH nodes hands its sweep inputs over in LDS
+// (Stash); otherwise the two halves share the LDS and the sweep loads them.
 template <typename T, typename Y, int KP, int NXL, int BCH, int FCH>
 __global__ __launch_bounds__(kBlock, (iter_min_blocks<T, Y, KP, NXL, FCH>())) void k_iter(
     SysDev<T> sys, const TreeDev<T, Y>* __restrict__ trees, const WorkItem* __restrict__ items,
-    const double* __restrict__ ctab, int32_t* __restrict__ done_out) {
+    const double* __restrict__ ctab, int32_t* __restrict__ done_out, int stash_arg) {
   constexpr int NT = KP / 64, KS = KP / 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_last;
@@ -1272,7 +1487,13 @@ __global__ __launch_bounds__(kBlock, (iter_min_blocks<T, Y, KP, NXL, FCH>())) vo
   RowCache<T, kNnzBt> bt;
   Iter<T, Y> xb;
   ChainDesc leaf_desc;
-  fwd_item<T, Y, NXL, KP, FCH, true>(sys, fs, td, wi, st, xf, kModeAPG, smem_raw, s_last, done_out, [&] {
+  const bool stash = stash_arg != 0 && wi.len <= BCH;
+  T* sQs = reinterpret_cast<T*>(smem_raw);
+  T* sRs = sQs + 2 * BCH * 64 * NXL;
+  const Stash<T, Y> sh{stash ? sQs : nullptr, sRs, sRs + (size_t)KP * (BCH + 1), 64 * NXL, BCH + 1, BCH,
+                       (Y)gp(ctab)[xf.it + 1]};
+  unsigned char* fwd_lds = stash_arg != 0 ? smem_raw + lds_stash_offset(sys.nx, sys.nu, sizeof(T), BCH) : smem_raw;
+  fwd_item<T, Y, NXL, KP, FCH, true>(sys, fs, td, wi, st, xf, kModeAPG, fwd_lds, s_last, done_out, sh, [&] {
     bwd_load_regs<T, KP>(sys, preg, bt);
     xb = make_iter_at(td, st, ctab, kModeAPG, xf.it + 1);
     leaf_desc = gp(td.chains)[wi.chain];
@@ -1280,7 +1501,8 @@ __global__ __launch_bounds__(kBlock, (iter_min_blocks<T, Y, KP, NXL, FCH>())) vo
   __syncthreads();  // the LDS now holds the backward layout
   bwd_zero_rows<T, KP, NXL, BCH>(sys, smem_raw);
   int par = 0;
-  bwd_item<T, Y, KP, NXL, BCH, true>(sys, td, xb, kModeAPG, wi.chain, leaf_desc, smem_raw, preg, bt, par, s_last);
+  bwd_item<T, Y, KP, NXL, BCH, true>(sys, td, xb, kModeAPG, wi.chain, leaf_desc, smem_raw, preg, bt, par, s_last,
+                                     stash);
 }
 
 template <typename T>
@@ -1435,12 +1657,19 @@ hipError_t launch_forward(const SysDev<T>& sys, const TreeDev<T, Y>* trees, cons
 template <typename T, typename Y, int KP, int NXL, int BCH, int FCH>
 hipError_t launch_iter_ch(const SysDev<T>& sys, const TreeDev<T, Y>* trees, const WorkItem* items, int n_items,
                           const double* ctab, int32_t* done_out, hipStream_t s) {
-  const size_t lds = std::max(lds_bytes_forward(sys.nx, sys.nu, sizeof(T), FCH),
-                              lds_bytes_backward(sys.nx, sys.nu, sizeof(T), BCH));
+  // the LDS hand-over (both layouts side by side) is used where it leaves
+  // room for the workgroups per CU the kernel's registers allow (two with
+  // float64 solve steps, three with float32 ones)
+  const size_t lf = lds_bytes_forward(sys.nx, sys.nu, sizeof(T), FCH);
+  const size_t lb = lds_bytes_backward(sys.nx, sys.nu, sizeof(T), BCH);
+  const size_t both = lds_stash_offset(sys.nx, sys.nu, sizeof(T), BCH) + lf;
+  const int per_cu = iter_min_blocks<T, Y, KP, NXL, FCH>() == 1 ? 1 : (sizeof(T) == 8 ? 2 : 3);
+  const int stash = both <= (size_t)kLdsPerCu / per_cu ? 1 : 0;
+  const size_t lds = stash ? both : std::max(lf, lb);
   hipError_t e = allow_lds(k_iter<T, Y, KP, NXL, BCH, FCH>, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_iter<T, Y, KP, NXL, BCH, FCH>), dim3(n_items), dim3(kBlock), lds, s, sys, trees, items, ctab,
-                     done_out);
+                     done_out, stash);
   return hipGetLastError();
 }
 
