@@ -50,7 +50,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "apg_iteration_f64_barcelona7260_hbm_traffic.md")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "apg_iteration_hbm_traffic_tree7260_batch64.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1604_01074_amd", "csrc", "smpc_kernels.hip")
 METRIC = "APG iters/s + solves/s to tol 1e-3 (FP32 batched vs FP64 plain); p50/p99 latency"
 
@@ -401,13 +401,16 @@ def batched_leg(ctx, steps: int, max_iter: int, with_fp64: bool) -> dict:
     # iteration count, no stop test)
     ctx.reset_stats()
     ctx.profiling(True)
-    system.solve_batch(trees, ps, qs, tol=0.0, max_iter=60, check_every=10, precision=32, polish_iters=0,
-                       dual64=True, want_x=False, want_y=False, tune=1)
+    _, rr = system.solve_batch(trees, ps, qs, tol=0.0, max_iter=60, check_every=10, precision=32, polish_iters=0,
+                               dual64=True, want_x=False, want_y=False, tune=1)
     stats = ctx.kernel_stats()
     ctx.profiling(False)
     if "iter_mix" in stats:
         avg = stats["iter_mix"]["total_ms"] / stats["iter_mix"]["launches"]
-        out["fp32_bulk"]["roofline"] = roofline_entry("iter_mix", avg, nodes, nx, nu, ne, 4, None, dual_elem=8)
+        chunk = f"{rr[0]['chunk32'][0]},{rr[0]['chunk32'][1]}"
+        out["fp32_bulk"]["roofline"] = roofline_entry("iter_mix", avg, nodes, nx, nu, ne, 4,
+                                                      measured_traffic(f"iter_mix chunks {chunk}"), dual_elem=8)
+        out["fp32_bulk"]["roofline"]["chunk"] = chunk
     if with_fp64:
         res64, t64 = [], 0.0
         kw64 = dict(tol=1e-3, max_iter=max_iter, check_every=10, precision=64, want_x=False, want_y=False, tune=1)
