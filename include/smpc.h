@@ -46,6 +46,10 @@ enum {
   SMPC_OK = 0,
   SMPC_MAX_ITER = 1,        /* warning: max_iter reached before tol; outputs valid */
   SMPC_PENDING = 2,         /* smpc_server_poll: the request has not finished yet  */
+  SMPC_STALLED = 3,         /* warning: with stall_checks > 0, r_p made no progress
+                               for stall_checks checks (e.g. an infeasible coupling
+                               E u + Ed d = 0 in the u box, whose dual grows
+                               without bound); outputs valid                       */
   SMPC_EINVAL = -1,         /* bad argument (NULL, negative size, bad flag)        */
   SMPC_EDIM = -2,           /* dimension outside the supported range               */
   SMPC_ENOTSPD = -3,        /* Wu not symmetric positive definite                  */
@@ -172,7 +176,12 @@ int smpc_tree_info(smpc_tree* tree, int* M, int* N, int* n_chains, int* n_levels
  * below 0.99 of its best value for stall_checks consecutive checks has met
  * the accuracy floor of float32: that tree continues in float64 until the
  * stop test passes or max_iter is reached (stall_checks 0 -> 100, < 0 ->
- * never; not applied when tol = 0).  Reductions are float64 in both modes.
+ * never; not applied when tol = 0).  With stall_checks > 0 the same rule
+ * also ends a precision-64 solve with SMPC_STALLED: in float64 a stall means
+ * the iteration makes no progress, as when E u + Ed d = 0 has no solution in
+ * the u box (the dual then grows without bound while r_p levels off); the
+ * window must be longer than the plateaus of the accelerated iteration on
+ * the problems at hand.  Reductions are float64 in both modes.
  * warm_start: 0 -> y0 = 0; 1 -> y^0 = y^{-1} = the tree's resident dual of
  * its previous solve, shifted by smpc_shift_warm_start (no host copy);
  * 2 -> y^0 = y0 and y^{-1} = y_prev0 (or y0 when y_prev0 is NULL), both
@@ -229,7 +238,8 @@ int smpc_chunk_lengths(int precision, int which, int* out, int cap, int* n);
 /* Caller-allocated outputs; any pointer may be NULL.  u0: nu, x: M*nx,
  * u: M*nu (last primal iterate z^nu), y: M*(2nx+nu) (y^{nu+1}).
  * iterations counts all iterations, fp32_iterations the float32 ones.
- * status: SMPC_OK (stop test passed), SMPC_MAX_ITER or SMPC_EDIVERGED.
+ * status: SMPC_OK (stop test passed), SMPC_MAX_ITER, SMPC_STALLED or
+ * SMPC_EDIVERGED.
  * cost and gap: with opts.gap = 1, the primal cost of z^nu and the duality
  * gap of smpc_tree_objective; 0 otherwise.                                  */
 typedef struct {

@@ -848,6 +848,15 @@ int stall_limit32(const smpc_solve_opts* o) {
   return o->stall_checks == 0 ? 100 : o->stall_checks;
 }
 
+// A float64 solve (precision 64) stops on a stall only when asked for
+// (stall_checks > 0): its r_p has no storage floor, so a stall means no
+// progress at all, as with an infeasible coupling, whose dual grows without
+// bound.  (The float64 finish after a float32 stall runs to the stop test:
+// the float32 window is short by design.)
+int stall_limit64(const smpc_solve_opts* o) {
+  return (o->tol > 0.0 && o->stall_checks > 0) ? o->stall_checks : 0;
+}
+
 int init_tree_state(smpc_tree* t, const smpc_solve_opts* o, int iter, int max_iter, double tol, int stall_limit) {
   TreeState h{};
   h.iter = iter;
@@ -894,7 +903,7 @@ int tree_begin(smpc_tree* t, const double* p, const double* q, const smpc_solve_
     SMPC_TRY(upload_dual_start<double>(t, y0, yp0));
   }
   if (ph.run32) return init_tree_state(t, o, 0, ph.max32, o->tol, stall_limit32(o));
-  return init_tree_state(t, o, 0, o->max_iter, o->tol, 0);
+  return init_tree_state(t, o, 0, o->max_iter, o->tol, stall_limit64(o));
 }
 
 // After the float32 phase: continue in float64 from the float32 iterates
@@ -937,10 +946,12 @@ int tree_result(smpc_tree* t, const smpc_solve_opts* o, int fp32_iters, int stat
   r->fp32_iterations = ph.run32 ? fp32_iters : 0;
   r->r_primal = h.r_p;
   r->hz_t_max = h.hzt;
+  // device status: 0 stop test passed, 1 iteration cap, 2 stalled, -9 diverged
+  auto pub = [](int st) { return st == 0 ? SMPC_OK : (st == 2 ? SMPC_STALLED : SMPC_MAX_ITER); };
   int status;
   if (h.status == -9 || (ph.run32 && status32 == -9)) status = SMPC_EDIVERGED;
-  else if (ph.run32 && status32 != 2) status = status32 == 0 ? SMPC_OK : SMPC_MAX_ITER;
-  else status = h.status == 0 ? SMPC_OK : SMPC_MAX_ITER;
+  else if (ph.run32 && ph.run64 && status32 != 2) status = pub(status32);  // float32 phase, then the polish
+  else status = pub(h.status);
   r->status = status;
   if (ph.run64) SMPC_TRY(download_primal<double>(t, r->x, r->u, r->u0));
   else SMPC_TRY(download_primal<float>(t, r->x, r->u, r->u0));

@@ -17,10 +17,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsmpc.so")
 
-OK, MAX_ITER, PENDING = 0, 1, 2
+OK, MAX_ITER, PENDING, STALLED = 0, 1, 2, 3
 EINVAL, EDIM, ENOTSPD, ERANK, EPROB, ENOMEM, EDEVICE, ENOTFACTORED, EDIVERGED, ENAN, ECANCELED = range(-1, -12, -1)
 STATUS_NAMES = {
-    0: "SMPC_OK", 1: "SMPC_MAX_ITER", 2: "SMPC_PENDING", -1: "SMPC_EINVAL", -2: "SMPC_EDIM", -3: "SMPC_ENOTSPD",
+    0: "SMPC_OK", 1: "SMPC_MAX_ITER", 2: "SMPC_PENDING", 3: "SMPC_STALLED", -1: "SMPC_EINVAL", -2: "SMPC_EDIM", -3: "SMPC_ENOTSPD",
     -4: "SMPC_ERANK", -5: "SMPC_EPROB", -6: "SMPC_ENOMEM", -7: "SMPC_EDEVICE",
     -8: "SMPC_ENOTFACTORED", -9: "SMPC_EDIVERGED", -10: "SMPC_ENAN", -11: "SMPC_ECANCELED",
 }

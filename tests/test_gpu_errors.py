@@ -113,3 +113,57 @@ def test_max_iter_status_and_divergence_flag(S, ctx):
     finally:
         S.smpc_tree_destroy(tr)
         S.smpc_sys_destroy(s)
+
+
+def test_infeasible_coupling_stops_with_a_status(S, ctx):
+    """Demands ten times those drawn leave E u + Ed d = 0 with no solution in
+    the u box at every node (certified by a linear program, independently of
+    the library): the problem is infeasible and its dual unbounded.  With
+    stall_checks the float64 solve stops with SMPC_STALLED well before
+    max_iter, and the dual keeps growing with the iteration count; the same
+    tree with the demands as drawn (feasible at every node) converges.  The
+    stall window (500 checks) is longer than the plateaus of the accelerated
+    iteration on the feasible problem, whose r_p falls about threefold per
+    16 000 iterations late on; on the infeasible one r_p settles near 9 after
+    about 2 000 iterations while |y| grows fourfold per doubling."""
+    from scipy.optimize import linprog
+
+    inst = ds.random_small_instance(1, nx=4, nu=5, nd=3, ne=2, N=6, branching=(2,))
+    sysd, tree = inst.sys, inst.tree
+    E, Ed = sysd["E"], sysd["Ed"]
+    box = list(zip(sysd["umin"], sysd["umax"]))
+
+    def lp_status(d0):
+        return linprog(np.zeros(E.shape[1]), A_eq=E, b_eq=-Ed @ d0, bounds=box, method="highs").status
+
+    assert all(lp_status(d) == 0 for d in inst.d)
+    bad = 10.0 * inst.d
+    assert all(lp_status(d) == 2 for d in bad)  # 2: infeasible
+    s = S.smpc_sys_create(ctx, sysd)
+    tr = S.smpc_tree_create(s, inst.N, tree["stage"], tree["parent"], tree["prob"])
+    dims = (inst.M, sysd["nx"], sysd["nu"])
+    try:
+        S.smpc_tree_set_data(tr, inst.d)
+        S.smpc_factor(tr, power_iters=200)
+        r = S.smpc_solve(tr, inst.p, inst.q, dims=dims, tol=1e-4, max_iter=60000, stall_checks=500)
+        print(f"[infeasible] feasible demands: status {r['status']} after {r['iterations']}", flush=True)
+        assert r["status"] == S.OK
+        S.smpc_tree_set_data(tr, bad)
+        r = S.smpc_solve(tr, inst.p, inst.q, dims=dims, tol=1e-4, max_iter=60000, stall_checks=500)
+        print(f"[infeasible] infeasible demands: status {r['status']} after {r['iterations']}, "
+              f"r_p {r['r_primal']:.3e}", flush=True)
+        assert r["status"] == S.STALLED and r["iterations"] < 20000
+        assert np.all(np.isfinite(r["u0"])) and np.all(np.isfinite(r["y"]))
+        norms = []
+        for its in (2000, 4000):
+            rr = S.smpc_solve(tr, inst.p, inst.q, dims=dims, tol=0.0, max_iter=its)
+            assert rr["status"] == S.MAX_ITER
+            norms.append(np.linalg.norm(rr["y"]))
+        print(f"[infeasible] |y| after 2000 / 4000 iterations: {norms[0]:.3e} / {norms[1]:.3e}", flush=True)
+        assert norms[1] > 1.5 * norms[0]
+        # without the rule the solve runs to its cap and says so
+        r = S.smpc_solve(tr, inst.p, inst.q, dims=dims, tol=1e-4, max_iter=3000)
+        assert r["status"] == S.MAX_ITER and r["iterations"] == 3000
+    finally:
+        S.smpc_tree_destroy(tr)
+        S.smpc_sys_destroy(s)
