@@ -271,10 +271,12 @@ __host__ __device__ inline size_t lds_stash_offset(int nx, int nu, size_t elem, 
 }
 
 __host__ __device__ inline size_t lds_bytes_forward(int nx, int nu, size_t elem, int chunk) {
-  // ut of two chunks (2 x chunk x padded nu), scales and pi of two chunks,
-  // the x carries of waves 0 and 1 (general A), 32 float64 reduction slots
+  // ut of two chunks (2 x chunk x padded nu), the scales of two chunks, the
+  // x carries of waves 0 and 1 (general A), the per-node prox scalars of two
+  // chunks (4 per node, room for float64), 32 float64 reduction slots
   const size_t ch = (size_t)chunk;
-  return elem * (2 * ch * (size_t)p_stride(nu) + 8 * ch + 2 * (size_t)nx) + 32 * sizeof(double);
+  return elem * (2 * ch * (size_t)p_stride(nu) + 8 * ch + 2 * (size_t)nx) + 8 * ch * sizeof(double) +
+         32 * sizeof(double);
 }
 
 

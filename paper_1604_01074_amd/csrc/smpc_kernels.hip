@@ -199,8 +199,8 @@ __device__ __forceinline__ void load_row(RowCache<T, K>& r, const int32_t* rp, c
 // DPP moves within rows of 16 lanes (gfx9 encodings).
 constexpr int kDppQuadSwap1 = 0xB1;  // quad_perm [1, 0, 3, 2]
 constexpr int kDppQuadSwap2 = 0x4E;  // quad_perm [2, 3, 0, 1]
-constexpr int kDppRowRor4 = 0x124;
-constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowMirror = 0x140;      // lane i of a row takes lane 15 - i
+constexpr int kDppRowHalfMirror = 0x141;  // lane i of a half row takes lane 7 - i
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v) {
@@ -226,16 +226,80 @@ __device__ __forceinline__ double read_lane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Sum over the 64 lanes of a wave, returned to every lane; every lane must be
-// active.  Butterflies inside each row of 16 lanes on the DPP path, then the
-// four row sums in a fixed order.
-template <typename T>
-__device__ __forceinline__ T wave_allsum(T v) {
-  v += dpp_mov<kDppQuadSwap1>(v);
-  v += dpp_mov<kDppQuadSwap2>(v);
-  v += dpp_mov<kDppRowRor4>(v);
-  v += dpp_mov<kDppRowRor8>(v);
-  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+// v plus the value of the partner lane 16 (HALF: 32) lanes away, for v equal
+// in all lanes of each row (HALF: each half wave): v_permlane16_swap hands
+// each row of one copy the value of the partner row, so the two copies'
+// sum holds the same two addends, in the same order, in every lane.
+template <bool HALF>
+__device__ __forceinline__ float add_partner(float v) {
+  const unsigned u = __float_as_uint(v);
+  if constexpr (HALF) {
+    const auto p = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  } else {
+    const auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  }
+}
+
+template <bool HALF>
+__device__ __forceinline__ double add_partner(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  auto join = [](unsigned h, unsigned l) {
+    return __longlong_as_double((long long)(((unsigned long long)h << 32) | l));
+  };
+  if constexpr (HALF) {
+    const auto pl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return join(ph[0], pl[0]) + join(ph[1], pl[1]);
+  } else {
+    const auto pl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto ph = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return join(ph[0], pl[0]) + join(ph[1], pl[1]);
+  }
+}
+
+// Sums over the 64 lanes of a wave of N values at once, each returned to
+// every lane; every lane must be active.  Each step adds two copies of the
+// same partial sum (xor partners within quads, mirrored quads within half
+// rows, mirrored half rows within rows, then partner rows and halves), so
+// every lane holds the same bits at every step.  The N sums are independent
+// and each step is taken for all of them before the next, so that their
+// latencies overlap.
+template <typename T, int N>
+__device__ __forceinline__ void wave_allsum(T (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<kDppQuadSwap1>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<kDppQuadSwap2>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<kDppRowHalfMirror>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<kDppRowMirror>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = add_partner<false>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = add_partner<true>(v[i]);
+}
+
+// 1/sqrt(v) for finite v > 0: the hardware estimate refined by Newton steps
+// on y^-2 = v, each of which doubles the correct bits (two in float64, one in
+// float32).  v = 0 gives a NaN; callers select around it.
+__device__ __forceinline__ double rsqrt_refined(double v) {
+  double y = __builtin_amdgcn_rsq(v);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const double e = __builtin_fma(-v * y, y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+__device__ __forceinline__ float rsqrt_refined(float v) {
+  const float y = __builtin_amdgcn_rsqf(v);
+  const float e = __builtin_fmaf(-v * y, y, 1.0f);
+  return __builtin_fmaf(0.5f * y, e, y);
 }
 
 // Per-workgroup view of one iteration of one tree.  T is the precision of
@@ -913,18 +977,20 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T, Y>& x, int
 // published.  Phase A runs x_n = A x_above + B ut_n + e_n for every node of
 // the chunk (with A = I the B ut terms of all nodes are formed first; only
 // the running sum is sequential).  Phase B applies the distance prox of
-// block b to every node at once -- the block norms, square roots and
-// divisions of different nodes are independent, so they overlap -- and
-// stores the dual update and primal output of the owned nodes.  Every value
-// is computed by the same expression as node by node.
+// block b to every node at once -- the block norms and inverse square roots
+// of different nodes are independent, so they overlap; each node's
+// (1 / lambda) / s and radius come from LDS (sFT, staged by waves 2 and 3) --
+// and stores the dual update and primal output of the owned nodes.  Every
+// value is computed by the same expression as node by node.
 template <typename T, typename Y, int NXL, int UP, int CH, bool AG>
 __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, const Iter<T, Y>& x, int b, int32_t cl,
                                                 int C, int npath,
                                                 const T (&ev)[NXL][CH], const Y (&wv)[NXL][CH],
                                                 const Y (&yv)[NXL][CH], T* stq, int sxs, Y cn,
                                                 const RowCache<T, kNnzB> (&brow)[NXL], const T (&bnd)[NXL][2],
-                                                const T* sSP, G<Y>* __restrict__ ynew, G<T>* __restrict__ z,
-                                                const T* sUp, T* cx, T (&xc)[NXL], Partials& pt) {
+                                                const T* sSP, const Y* sFT, G<Y>* __restrict__ ynew,
+                                                G<T>* __restrict__ z, const T* sUp, T* cx, T (&xc)[NXL],
+                                                Partials& pt) {
   constexpr int US = UP;
   const int lane = threadIdx.x & 63;
   const int nx = sys.nx, nu = sys.nu, D = sys.D;
@@ -1032,41 +1098,54 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
   // phase B (APG): the prox and the dual update of every node, branch-free
   // (nodes past the chunk's end and nodes owned elsewhere are computed too,
   // never stored, and enter the maxima as zeros, which leaves them
-  // unchanged); pin() keeps the compiler from sinking this work into the
-  // per-node store branches below, where it would run node by node.  The
-  // prox and the update run in the dual's precision Y.
+  // unchanged).  The loop has no branch, so the nodes' chains (block norm,
+  // inverse square root, step) form one scheduling region and overlap;
+  // pin() keeps the compiler from sinking this work into the per-node store
+  // branches below, where it would run node by node.  The prox and the
+  // update run in the dual's precision Y.
+  // bit cc: entry k0 + cc exists and is owned by this chain (wave-uniform)
+  const uint64_t live = __ballot(cl < 0) & ((1ull << C) - 1);
+  // Nodes are taken in groups of G whose chains overlap (all of the chunk,
+  // or one at a time where the registers would not hold more).
+  constexpr int G = pin_per_node<T, Y, NXL, CH>() ? 1 : CH;
   Y val[NXL][CH];
 #pragma unroll
-  for (int cc = 0; cc < CH; ++cc) {
-    const bool keep = cc < C && chunk_code(cl, cc) < 0;  // wave-uniform
-    const T s = sSP[4 * cc + b];
-    const Y f = x.ilam / (Y)s;
-    Y a[NXL], pa[NXL];
-    Y dsq = Y(0);
+  for (int g0 = 0; g0 < CH; g0 += G) {
+    // the prox input a = (w / lambda + s Hz) / s, its projection pa on the
+    // block's set and the squared distance, for every node of the group
+    Y a[NXL][G], pa[NXL][G], dsq[G];
 #pragma unroll
-    for (int r = 0; r < NXL; ++r) {
-      a[r] = (Y)xs[r][cc] + wv[r][cc] * f;  // (w / lambda + s Hz) / s
-      const Y lo = (Y)bnd[r][0], hi = (Y)bnd[r][1];
-      pa[r] = b == 0 ? (a[r] > lo ? a[r] : lo) : clampv(a[r], lo, hi);
-      const Y d = lane + 64 * r < nx ? a[r] - pa[r] : Y(0);
-      dsq += d * d;
+    for (int c = 0; c < G; ++c) {
+      const int cc = g0 + c;
+      const Y f = sFT[4 * cc + b];  // (1 / lambda) / s
+      dsq[c] = Y(0);
+#pragma unroll
+      for (int r = 0; r < NXL; ++r) {
+        a[r][c] = (Y)xs[r][cc] + wv[r][cc] * f;
+        const Y lo = (Y)bnd[r][0], hi = (Y)bnd[r][1];
+        pa[r][c] = b == 0 ? (a[r][c] > lo ? a[r][c] : lo) : clampv(a[r][c], lo, hi);
+        const Y d = lane + 64 * r < nx ? a[r][c] - pa[r][c] : Y(0);
+        dsq[c] += d * d;
+      }
     }
-    const Y del = sqrt(wave_allsum(dsq));
-    const Y pi_n = b == 0 && sys.safety_by_prob ? (Y)sSP[4 * cc + 3] : Y(1);
-    const Y cb = b == 0 ? (Y)sys.W_x * pi_n : (Y)sys.gamma_d;
-    const Y tau = cb * x.ilam / ((Y)s * (Y)s);
-    const Y k = del <= tau ? Y(1) : tau / del;
+    wave_allsum(dsq);
+    // the distance against the radius tau: inside, the projection; outside,
+    // the step of length tau towards it
 #pragma unroll
-    for (int r = 0; r < NXL; ++r) {
-      const bool in = keep && lane + 64 * r < nx;
-      const Y t = del <= tau ? pa[r] : a[r] - k * (a[r] - pa[r]);
-      val[r][cc] = wv[r][cc] + x.lam * (Y)s * ((Y)xs[r][cc] - t);
-      fold_max(pt, in ? (double)xs[r][cc] : 0.0, in ? (double)t : 0.0);
-      if constexpr (pin_per_node<T, Y, NXL, CH>()) pin(val[r][cc]);
-      // a node of this chain: the next sweep's xi_n part of block b
-      if (stq != nullptr && cc >= npath && cc < C && lane + 64 * r < nx) {
-        const Y v = val[r][cc];
-        stq[(cc - npath) * sxs + lane + 64 * r] = scaled<T, Y>(s, extrapolate(v, yv[r][cc], cn));
+    for (int c = 0; c < G; ++c) {
+      const int cc = g0 + c;
+      const bool keep = (live >> cc) & 1;
+      const T s = sSP[4 * cc + b];
+      const Y tau = sFT[4 * cc + 2 + b];  // c_b (1 / lambda) / s^2
+      const bool inside = dsq[c] <= tau * tau;
+      const Y k = tau * rsqrt_refined(dsq[c]);
+#pragma unroll
+      for (int r = 0; r < NXL; ++r) {
+        const bool in = keep && lane + 64 * r < nx;
+        const Y t = inside ? pa[r][c] : a[r][c] - k * (a[r][c] - pa[r][c]);
+        val[r][cc] = wv[r][cc] + x.lam * (Y)s * ((Y)xs[r][cc] - t);
+        fold_max(pt, in ? (double)xs[r][cc] : 0.0, in ? (double)t : 0.0);
+        if constexpr (pin_per_node<T, Y, NXL, CH>()) pin(val[r][cc]);
       }
     }
   }
@@ -1075,6 +1154,18 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
     for (int cc = 0; cc < CH; ++cc)
 #pragma unroll
       for (int r = 0; r < NXL; ++r) pin(val[r][cc]);
+  }
+  // the chain's own nodes: the next sweep's xi_n part of block b
+  if (stq != nullptr) {
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) {
+      if (cc < npath || cc >= C) continue;  // wave-uniform
+      const T s = sSP[4 * cc + b];
+#pragma unroll
+      for (int r = 0; r < NXL; ++r)
+        if (lane + 64 * r < nx)
+          stq[(cc - npath) * sxs + lane + 64 * r] = scaled<T, Y>(s, extrapolate(val[r][cc], yv[r][cc], cn));
+    }
   }
 #pragma unroll
   for (int cc = 0; cc < CH; ++cc) {
@@ -1143,8 +1234,9 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T,
   const int j = tid - 128;
   const bool ju = wave >= 2 && j < nu;
   T* sU = reinterpret_cast<T*>(smem_raw);  // 2 x CH x UP (UP >= nu, a constant)
-  T* sSP = sU + 2 * CH * UP;               // 2 x CH x 4: scales and pi of the chunk's nodes
+  T* sSP = sU + 2 * CH * UP;               // 2 x CH x 4: the scales of the chunk's nodes
   T* sXc = sSP + 2 * 4 * CH;               // 2 x nx (general A: carries of waves 0, 1)
+  Y* sFT = reinterpret_cast<Y*>(sXc + 2 * nx);  // 2 x CH x 4: (1/lambda)/s and radii of both blocks
   // every wave keeps the node codes of the current and the next chunk in
   // registers (lane k: entry k0 + k, resp. k0 + CH + k; entries past the
   // sequence repeat its last node) and loads the codes one chunk further
@@ -1198,34 +1290,41 @@ __device__ __forceinline__ void fwd_nodes(const SysDev<T>& sys, const TreeDev<T,
     }
     T* sUp = sU + par * CH * UP;
     T* sSPp = sSP + par * 4 * CH;
-    // wave 2 stages the scales and pi of the chunk's nodes (lane k: entry
-    // k0 + k) around its own loads, so that waves 0 and 1 never wait for them
-    const bool spl = wave == 2 && lane < C;
-    T sp0 = T(1), sp1 = T(1), sp3 = T(1);
+    Y* sFTp = sFT + par * 4 * CH;
+    // waves 2 (block 0) and 3 (block 1) stage the scale of their block for
+    // the chunk's nodes (lane k: entry k0 + k), with (1 / lambda) / s and the
+    // prox radius c_b (1 / lambda) / s^2 (c_0 = W_x, times pi_n when the
+    // safety term is weighted by probability; c_1 = gamma_d), around their own
+    // loads, so that waves 0 and 1 neither wait for them nor divide
+    const bool spl = wave >= 2 && lane < C;
+    const int sb = wave - 2;
+    T sp = T(1), sp3 = T(1);
     if (spl) {
       const uint32_t n = (uint32_t)(cur < 0 ? -1 - cur : cur);
-      if (x.scaled) {
-        sp0 = gp(td.scale)[n * 3];
-        sp1 = gp(td.scale)[n * 3 + 1];
-      }
-      sp3 = gp(td.pi)[n];
+      if (x.scaled) sp = gp(td.scale)[n * 3 + sb];
+      if (sb == 0) sp3 = gp(td.pi)[n];
     }
     if (ju)
       fwd_psi_chunk<T, Y, UP, CH, AG>(mode, x, cur, C, npath, j, nx, nu, D, gp(td.du), gp(td.uhat), x.ycur,
                                       x.yprv, gp(td.scale), gp(td.beta), x.ynew, gp(td.z), sUp, utc, ubnd[0],
                                       ubnd[1], sh, pt);
     if (spl) {
-      sSPp[4 * lane] = sp0;
-      sSPp[4 * lane + 1] = sp1;
-      sSPp[4 * lane + 3] = sp3;
-      if (sh.q != nullptr && lane >= npath) sh.inv[lane - npath] = T(-0.5) / sp3;  // a node of this chain
+      sSPp[4 * lane + sb] = sp;
+      if (mode == kModeAPG) {
+        const Y ys = (Y)sp;
+        const Y pi_n = sb == 0 && sys.safety_by_prob ? (Y)sp3 : Y(1);
+        const Y cb = sb == 0 ? (Y)sys.W_x * pi_n : (Y)sys.gamma_d;
+        sFTp[4 * lane + sb] = x.ilam / ys;
+        sFTp[4 * lane + 2 + sb] = cb * x.ilam / (ys * ys);
+      }
+      if (sb == 0 && sh.q != nullptr && lane >= npath) sh.inv[lane - npath] = T(-0.5) / sp3;  // a node of this chain
     }
     __syncthreads();  // ut and the scales of the chunk published
     if (wave < 2) {
       if (!PF) dual_point();
       fwd_state_chunk<T, Y, NXL, UP, CH, AG>(sys, mode, x, b, cur, C, npath, Lc.e, wv, Lc.y,
                                              sh.q != nullptr ? sh.q + (size_t)b * sh.bch * sh.xs : nullptr, sh.xs,
-                                             sh.cn, brow, bnd, sSPp, x.ynew, gp(td.z), sUp,
+                                             sh.cn, brow, bnd, sSPp, sFTp, x.ynew, gp(td.z), sUp,
                                              sXc + (size_t)wave * nx, xc, pt);
     }
     par ^= 1;
@@ -1248,11 +1347,6 @@ constexpr int fwd_min_blocks() {
   return (NXL > 1 && CH * sizeof(Y) > 32) ? 1 : 2;
 }
 
-// The forward rollout and prox of one leaf chain (with its root path), its
-// residual partials, and -- in the tree's last workgroup -- the end of the
-// iteration (stop test, counters).  AG: the ancestors' dual entries this
-// chain owns are stored at device scope (the fused iteration reads them in
-// the same launch).
 // Per-thread system rows and bounds of the thread's role in the forward
 // rollout.  They depend on the system only, so kernels load them first,
 // while the work item, tree and tree state are still on their way.
@@ -1282,6 +1376,11 @@ __device__ __forceinline__ void fwd_sys_loads(const SysDev<T>& sys, FwdSys<T, NX
   f.ubnd[1] = (wave >= 2 && j < nu) ? gp(sys.umax)[j] : T(0);
 }
 
+// The forward rollout and prox of one leaf chain (with its root path), its
+// residual partials, and -- in the tree's last workgroup -- the end of the
+// iteration (stop test, counters).  AG: the ancestors' dual entries this
+// chain owns are stored at device scope (the fused iteration reads them in
+// the same launch).
 template <typename T, typename Y, int NXL, int UP, int CH, bool AG, typename AfterRollout>
 __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, NXL>& fs, const TreeDev<T, Y>& td,
                                          const WorkItem wi, G<TreeState>* st, const Iter<T, Y>& x, int mode,
