@@ -473,15 +473,23 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
       T* sQw = sQ + wave * CH * XS;
       if (stashed) {
         // the raw xi parts are in place: with A = I the running sum over
-        // them (the general-A recursion below reads them as they are)
+        // them (the general-A recursion below reads them as they are), the
+        // reads of a batch of nodes issued together
         if (sys.a_identity) {
 #pragma unroll
           for (int r = 0; r < NXL; ++r) {
             const int i = lane + 64 * r;
             if (i < nx)
-              for (int cc = C - 1; cc >= 0; --cc) {
-                qc[r] += sQw[cc * XS + i];
-                sQw[cc * XS + i] = qc[r];
+              for (int g = C - 1; g >= 0; g -= kLoadBatch) {
+                T xi[kLoadBatch];
+#pragma unroll
+                for (int k = 0; k < kLoadBatch; ++k) xi[k] = sQw[(g - k >= 0 ? g - k : 0) * XS + i];
+#pragma unroll
+                for (int k = 0; k < kLoadBatch; ++k)
+                  if (g - k >= 0) {
+                    qc[r] += xi[k];
+                    sQw[(g - k) * XS + i] = qc[r];
+                  }
               }
           }
         }
@@ -614,19 +622,24 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
       // a short chain (one chunk for every chunk length, so the choice never
       // depends on the chunk length): du = -P rho / (2 pi) on the VALU from
       // the same register-resident P.  Lane l of wave w sums its K residue
-      // class, k = 4 st + l / 16, for columns 16 (w NT + t) + l % 16; the four
+      // class, k = 4 st + l / 16, for columns 16 (w NT + t) + l % 16, in four
+      // partial sums (st mod 4) fed by batches of eight LDS reads; the four
       // 16-lane rows are then added, (l, l ^ 16) + (l ^ 32, l ^ 48).
-#pragma unroll
       for (int cc = 0; cc < kValuChain; ++cc) {
         if (cc >= C) break;  // wave-uniform
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          T a = T(0);
+          T ps[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-          for (int st = 0; st < KS; ++st) {
-            a += preg[st * NT + t] * sRt[(4 * st + (lane >> 4)) * RS + cc];
-            if (st % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+          for (int g = 0; g < KS; g += 8) {
+            T rv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) rv[k] = sRt[(4 * (g + k) + (lane >> 4)) * RS + cc];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) ps[k & 3] = fmadd(preg[(g + k) * NT + t], rv[k], ps[k & 3]);
+            __builtin_amdgcn_sched_barrier(0);
           }
+          T a = (ps[0] + ps[1]) + (ps[2] + ps[3]);
           a += __shfl_xor(a, 16);
           a += __shfl_xor(a, 32);
           const int jj = 16 * (wave * NT + t) + (lane & 15);
@@ -636,35 +649,57 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
       par ^= 1;
       continue;
     }
-    // du = -P rho / (2 pi) on the matrix cores.  Rows cc >= C of the rho tile
-    // hold stale values: they only reach output rows that are not stored.
-    v4 acc[MT][NT];
+    // du = -P rho / (2 pi) on the matrix cores, in as many 16-row tiles as
+    // the chunk's rows need (rows at or past C of the last tile hold stale
+    // values: they only reach output rows that are not stored).  The A
+    // operands of a K step are read from LDS one step ahead of their use, so
+    // that the read is in flight while the step before runs.
+    const int ks_run = (nu + 3) >> 2;  // K steps that meet a row of P below nu
+    auto product = [&](auto tiles) {
+      constexpr int MR = decltype(tiles)::value;
+      v4 acc[MR][NT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+      for (int m = 0; m < MR; ++m)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[m][t] = v4{T(0), T(0), T(0), T(0)};
+        for (int t = 0; t < NT; ++t) acc[m][t] = v4{T(0), T(0), T(0), T(0)};
+      T an[MR];
 #pragma unroll
-    for (int st = 0; st < KS; ++st) {
-      T a[MT];
+      for (int m = 0; m < MR; ++m) an[m] = sRt[(lane >> 4) * RS + 16 * m + (lane & 15)];
 #pragma unroll
-      for (int m = 0; m < MT; ++m) a[m] = sRt[(4 * st + (lane >> 4)) * RS + 16 * m + (lane & 15)];
+      for (int st = 0; st < KS; ++st) {
+        T a[MR];
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+        for (int m = 0; m < MR; ++m) a[m] = an[m];
+        if (st + 1 < KS) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) acc[m][t] = Mfma<T>::op(a[m], preg[st * NT + t], acc[m][t]);
-      if (st % 8 == 7) __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int jj = 16 * (wave * NT + t) + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int cc = 16 * m + Mfma<T>::row(lane, r);
-          if (cc < C && jj < nu) gp(td.du)[(uint32_t)(nb + cc) * (uint32_t)nu + jj] = acc[m][t][r] * sIp[cc];
+          for (int m = 0; m < MR; ++m) an[m] = sRt[(4 * (st + 1) + (lane >> 4)) * RS + 16 * m + (lane & 15)];
         }
+        // a step whose rows of P all lie at or past nu adds zeros and is
+        // skipped (only in the second half: KP is the least of 64, 128 >= nu)
+        if (st < KS / 2 || st < ks_run) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int m = 0; m < MR; ++m) acc[m][t] = Mfma<T>::op(a[m], preg[st * NT + t], acc[m][t]);
+        }
+        if (st % 8 == 7) __builtin_amdgcn_sched_barrier(0);
       }
+#pragma unroll
+      for (int m = 0; m < MR; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int jj = 16 * (wave * NT + t) + (lane & 15);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int cc = 16 * m + Mfma<T>::row(lane, r);
+            if (cc < C && jj < nu) gp(td.du)[(uint32_t)(nb + cc) * (uint32_t)nu + jj] = acc[m][t][r] * sIp[cc];
+          }
+        }
+    };
+    if (MT > 1 && C <= 16)
+      product(std::integral_constant<int, 1>{});
+    else
+      product(std::integral_constant<int, MT>{});
     par ^= 1;
   }
   // top node of the chain: hand Q (both parts) and rho to the parent chain
