@@ -402,11 +402,15 @@ namespace {
 // ---------------------------------------------------------------------------
 // stashed: the forward half of this launch has left the chain's xi, r and
 // -1/(2 pi) in LDS (a leaf chain of at most CH nodes; see Stash), so the
-// loads are skipped.
+// loads are skipped.  pcnt: the parent chain's count of swept children (null
+// for the root chain) and pkids its number of children; the chain counts
+// itself done there once its top terms are stored, before the last chunk's
+// P product, and s_last tells (after a barrier) whether it was the last.
 template <typename T, typename Y, int KP, int NXL, int CH, bool AG>
 __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T, Y>& td, const Iter<T, Y>& x, int mode, int chain,
                           const ChainDesc ch, unsigned char* smem_raw, const T (&preg)[KP / 4 * (KP / 64)],
-                          const RowCache<T, kNnzBt>& bt, int& par, bool stashed) {
+                          const RowCache<T, kNnzBt>& bt, int& par, bool stashed, int* pcnt, int pkids,
+                          int& s_last) {
   constexpr int RS = CH + 1;  // row stride of the transposed rho (bank spread)
   constexpr int NT = KP / 64, KS = KP / 4, MT = CH / 16;
   constexpr int XS = 64 * NXL;  // row stride of the Q parts (>= nx, a constant)
@@ -579,7 +583,22 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
         __builtin_amdgcn_sched_barrier(0);
       }
     }
+    if (k0 == 0 && wave == 1) {
+      // the chain's top node: wave 1's part of Q for wave 0 to hand up
+#pragma unroll
+      for (int r = 0; r < NXL; ++r)
+        if (lane + 64 * r < nx) sTop[lane + 64 * r] = qc[r];
+    }
     __syncthreads();  // Q parts complete
+    // the last chunk holds the chain's top node: Q (both parts) goes up to
+    // the parent chain now, rho right after its recursion, so that both
+    // stores drain while the sweep goes on
+    if (k0 == 0 && wave == 0) {
+#pragma unroll
+      for (int r = 0; r < NXL; ++r)
+        if (lane + 64 * r < nx)
+          st_agent(&td.ctopQ[(size_t)chain * nx + lane + 64 * r], qc[r] + sTop[lane + 64 * r]);
+    }
     if (ju) {
       // rho recursion, bottom node first: r_n + B' Q_n + rho_below.  The
       // terms r_n + B' Q_n of a group of nodes are formed first, in one
@@ -616,8 +635,28 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
           sRt[j * RS + cc] = rc;
         }
       }
+      if (k0 == 0) st_agent(&td.ctopR[(size_t)chain * nu + j], rc);
     }
     __syncthreads();  // sRt complete
+    // In the last chunk the chain counts itself done at the parent once the
+    // top terms are stored: the count is issued partway through the P
+    // product (the stores have drained meanwhile) and its answer read after
+    // it, before the du stores (which would otherwise have to drain first).
+    const bool counting = k0 == 0 && pcnt != nullptr;  // workgroup-uniform
+    int prev = 0;
+    auto count_issue = [&] {
+      if (counting) {
+        wait_mem();
+        __syncthreads();
+        if (tid == 0) prev = __hip_atomic_fetch_add(pcnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    };
+    auto count_answer = [&] {
+      if (counting && tid == 0) {
+        s_last = (prev == pkids - 1);
+        if (s_last) __hip_atomic_store(pcnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next iteration
+      }
+    };
     if (ch.len <= kValuChain) {
       // a short chain (one chunk for every chunk length, so the choice never
       // depends on the chunk length): du = -P rho / (2 pi) on the VALU from
@@ -627,6 +666,7 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
       // 16-lane rows are then added, (l, l ^ 16) + (l ^ 32, l ^ 48).
       for (int cc = 0; cc < kValuChain; ++cc) {
         if (cc >= C) break;  // wave-uniform
+        T res[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           T ps[4] = {T(0), T(0), T(0), T(0)};
@@ -642,8 +682,14 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
           T a = (ps[0] + ps[1]) + (ps[2] + ps[3]);
           a += __shfl_xor(a, 16);
           a += __shfl_xor(a, 32);
+          res[t] = a;
+          if (cc == 0 && t == 0) count_issue();
+        }
+        if (cc == 0) count_answer();
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
           const int jj = 16 * (wave * NT + t) + (lane & 15);
-          if (lane < 16 && jj < nu) gp(td.du)[(uint32_t)(nb + cc) * (uint32_t)nu + jj] = a * sIp[cc];
+          if (lane < 16 && jj < nu) gp(td.du)[(uint32_t)(nb + cc) * (uint32_t)nu + jj] = res[t] * sIp[cc];
         }
       }
       par ^= 1;
@@ -683,7 +729,9 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
             for (int m = 0; m < MR; ++m) acc[m][t] = Mfma<T>::op(a[m], preg[st * NT + t], acc[m][t]);
         }
         if (st % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+        if (st == KS / 2) count_issue();
       }
+      count_answer();
 #pragma unroll
       for (int m = 0; m < MR; ++m)
 #pragma unroll
@@ -701,21 +749,6 @@ __device__ __forceinline__ void bwd_chain(const SysDev<T>& sys, const TreeDev<T,
     else
       product(std::integral_constant<int, MT>{});
     par ^= 1;
-  }
-  // top node of the chain: hand Q (both parts) and rho to the parent chain
-  if (wave == 1) {
-#pragma unroll
-    for (int r = 0; r < NXL; ++r)
-      if (lane + 64 * r < nx) sTop[lane + 64 * r] = qc[r];
-  }
-  __syncthreads();
-  if (wave == 0) {
-#pragma unroll
-    for (int r = 0; r < NXL; ++r)
-      if (lane + 64 * r < nx)
-        st_agent(&td.ctopQ[(size_t)chain * nx + lane + 64 * r], qc[r] + sTop[lane + 64 * r]);
-  } else if (ju) {
-    st_agent(&td.ctopR[(size_t)chain * nu + j], rc);
   }
 }
 
@@ -754,30 +787,24 @@ __device__ __forceinline__ void bwd_item(const SysDev<T>& sys, const TreeDev<T, 
                                          int leaf, const ChainDesc leaf_desc, unsigned char* smem_raw,
                                          const T (&preg)[KP / 4 * (KP / 64)], const RowCache<T, kNnzBt>& bt,
                                          int& par, int& s_last, bool leaf_stashed = false) {
-  const int tid = threadIdx.x;
   int chain = leaf;
   ChainDesc ch = leaf_desc;
   while (true) {
+    // the parent's descriptor (its number of children decides the count) is
+    // fetched while this chain is swept
+    const int parent = ch.parent;
+    ChainDesc pdesc = ch;
+    if (parent >= 0) pdesc = gp(td.chains)[parent];
+    int* pcnt = parent >= 0 ? gp(td.cnt) + parent : nullptr;
     if (AGP && chain != leaf)
-      bwd_chain<T, Y, KP, NXL, CH, true>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par, false);
+      bwd_chain<T, Y, KP, NXL, CH, true>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par, false, pcnt,
+                                         pdesc.child_count, s_last);
     else
       bwd_chain<T, Y, KP, NXL, CH, false>(sys, td, x, mode, chain, ch, smem_raw, preg, bt, par,
-                                          leaf_stashed && chain == leaf);
-    const int parent = ch.parent;
+                                          leaf_stashed && chain == leaf, pcnt, pdesc.child_count, s_last);
     if (parent < 0) break;  // the root chain is done: the sweep is complete
-    // the parent's descriptor is fetched while this chain's stores drain
-    const ChainDesc pdesc = gp(td.chains)[parent];
-    // this chain's top terms are stored: count this child done at the parent
-    wait_mem();
-    __syncthreads();
-    if (tid == 0) {
-      const int pc = pdesc.child_count;
-      const int prev = __hip_atomic_fetch_add(gp(td.cnt) + parent, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_last = (prev == pc - 1);
-      if (s_last) __hip_atomic_store(gp(td.cnt) + parent, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // ready for the next iteration
-    }
-    __syncthreads();
-    if (!s_last) break;  // a sibling is still running; it will sweep the parent
+    __syncthreads();        // the count's answer is published
+    if (!s_last) break;     // a sibling is still running; it will sweep the parent
     chain = parent;
     ch = pdesc;
   }
@@ -1492,15 +1519,38 @@ __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, N
   if (!s_last || wave != 0) return;
   const int it = x.it;
   if (mode == kModeAPG) {
-    const bool check = ((it + 1) % st->check_every == 0) || (it + 1 >= st->max_iter);
+    // every field of the tree's record the stop test reads, loaded together
+    const int check_every = st->check_every, max_iter = st->max_iter, stall_limit = st->stall_limit;
+    const int stall = st->stall;
+    const double tol = st->tol, best_rp = st->best_rp;
+    const bool check = ((it + 1) % check_every == 0) || (it + 1 >= max_iter);
     int done = 0;
     if (check) {
+      // the leaves' partials, a batch of eight per lane at a time: every
+      // chain index of the batch is loaded first, then every partial, so
+      // that each round of loads is in flight together (the maxima do not
+      // depend on the order)
       double rm = 0.0, hm = 0.0;
-      for (int k = lane; k < td.n_leaves; k += 64) {
-        const double* cs = td.cstat + (size_t)gp(td.leaves)[k] * kStat;
-        rm = nanmax(rm, ld_agent(&cs[0]));
-        hm = nanmax(hm, ld_agent(&cs[1]));
-        hm = nanmax(hm, ld_agent(&cs[2]));
+      for (int k0 = 0; k0 < td.n_leaves; k0 += 64 * 8) {
+        int lf[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + lane + 64 * u;
+          lf[u] = k < td.n_leaves ? gp(td.leaves)[k] : -1;
+        }
+        double v[8][3];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double* cs = td.cstat + (size_t)(lf[u] >= 0 ? lf[u] : 0) * kStat;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) v[u][q] = lf[u] >= 0 ? ld_agent(&cs[q]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          rm = nanmax(rm, v[u][0]);
+          hm = nanmax(hm, v[u][1]);
+          hm = nanmax(hm, v[u][2]);
+        }
       }
       rm = wave_nanmax(rm);
       hm = wave_nanmax(hm);
@@ -1511,21 +1561,24 @@ __device__ __forceinline__ void fwd_item(const SysDev<T>& sys, const FwdSys<T, N
         if (!finite) {
           done = 1;
           st->status = -9;
-        } else if (st->tol > 0.0 && rm <= st->tol * (1.0 + hm)) {
+        } else if (tol > 0.0 && rm <= tol * (1.0 + hm)) {
           done = 1;
           st->status = 0;
-        } else if (it + 1 >= st->max_iter) {
+        } else if (it + 1 >= max_iter) {
           done = 1;
           st->status = 1;
-        } else if (st->stall_limit > 0) {
+        } else if (stall_limit > 0) {
           // no new minimum of r_p for stall_limit checks: the iteration has
           // reached the accuracy floor of its number format
-          if (rm < 0.99 * st->best_rp) {
+          if (rm < 0.99 * best_rp) {
             st->best_rp = rm;
             st->stall = 0;
-          } else if (++st->stall >= st->stall_limit) {
-            done = 1;
-            st->status = 2;
+          } else {
+            st->stall = stall + 1;
+            if (stall + 1 >= stall_limit) {
+              done = 1;
+              st->status = 2;
+            }
           }
         }
         if (done) {
