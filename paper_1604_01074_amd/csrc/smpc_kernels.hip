@@ -215,17 +215,6 @@ __device__ __forceinline__ double dpp_mov(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-__device__ __forceinline__ float read_lane(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
-__device__ __forceinline__ double read_lane(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 // v plus the value of the partner lane 16 (HALF: 32) lanes away, for v equal
 // in all lanes of each row (HALF: each half wave): v_permlane16_swap hands
 // each row of one copy the value of the partner row, so the two copies'
