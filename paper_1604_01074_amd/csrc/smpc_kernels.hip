@@ -1206,6 +1206,32 @@ __device__ __forceinline__ void fwd_state_chunk(const SysDev<T>& sys, int mode, 
 #pragma unroll
       for (int r = 0; r < NXL; ++r) pin(val[r][cc]);
   }
+  // (one state row per lane, and for float64 short chunks: the other
+  // variants have no registers to spare for this path)
+  if (npath <= 0 && C == CH && NXL == 1 && (sizeof(T) == 4 || CH <= 4)) {
+    // wave-uniform: a full chunk of the chain's own nodes (all owned here,
+    // none an ancestor), so one lane test covers every store
+    const bool wz = x.write_z && b == 0;
+#pragma unroll
+    for (int r = 0; r < NXL; ++r) {
+      const int i = lane + 64 * r;
+      if (i < nx) {
+        // the next sweep's xi_n part of block b
+        if (stq != nullptr) {
+#pragma unroll
+          for (int cc = 0; cc < CH; ++cc)
+            stq[(cc - npath) * sxs + i] = scaled<T, Y>(sSP[4 * cc + b], extrapolate(val[r][cc], yv[r][cc], cn));
+        }
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          const uint32_t n = (uint32_t)(-1 - chunk_code(cl, cc));
+          if (wz) z[n * W + i] = xs[r][cc];
+          ynew[n * D + b * nx + i] = val[r][cc];
+        }
+      }
+    }
+    return;
+  }
   // the chain's own nodes: the next sweep's xi_n part of block b
   if (stq != nullptr) {
 #pragma unroll
