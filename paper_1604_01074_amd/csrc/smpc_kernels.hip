@@ -962,7 +962,7 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T, Y>& x, int
     Y val[CH];
 #pragma unroll
     for (int cc = 0; cc < CH; ++cc) {
-      const bool keep = cc < C && chunk_code(cl, cc) < 0;  // wave-uniform
+      const bool keep = (cc < C) & (chunk_code(cl, cc) < 0);  // wave-uniform, no branch
       if (cc < C) utc += duv[cc];
       sUp[cc * US + j] = utc;  // rows past the chunk's end are never read
       const T u = utc + uhv[cc];
@@ -973,15 +973,36 @@ __device__ __forceinline__ void fwd_psi_chunk(int mode, const Iter<T, Y>& x, int
       uv[cc] = u;
       val[cc] = w + x.lam * (Y)s * ((Y)u - t);
       fold_max(pt, keep ? (double)u : 0.0, keep ? (double)t : 0.0);
-      if constexpr (pin_per_node<T, Y, 1, CH>()) pin(val[cc]);
-      if (stash && cc >= npath && cc < C) {  // wave-uniform: a node of this chain
-        const Y v = val[cc];
-        sh.r[j * sh.rs + (cc - npath)] = beta_plus_scaled<T, Y>(bv[cc], s, extrapolate(v, yv[cc], sh.cn));
+      if constexpr (pin_per_node<T, Y, 1, CH>()) {
+        pin(val[cc]);
+        // the next sweep's r_n = beta_n + S w_psi, node by node here where
+        // the registers would not hold the chunk's inputs past the loop
+        if (stash && cc >= npath && cc < C)  // wave-uniform: a node of this chain
+          sh.r[j * sh.rs + (cc - npath)] = beta_plus_scaled<T, Y>(bv[cc], s, extrapolate(val[cc], yv[cc], sh.cn));
       }
     }
     if constexpr (!pin_per_node<T, Y, 1, CH>()) {
 #pragma unroll
       for (int cc = 0; cc < CH; ++cc) pin(val[cc]);
+    }
+    // the chain's own nodes: the next sweep's r_n = beta_n + S w_psi, after
+    // the loop so that it has no branch
+    if (!pin_per_node<T, Y, 1, CH>() && stash) {
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc)
+        if (cc >= npath && cc < C)  // wave-uniform: a node of this chain
+          sh.r[j * sh.rs + (cc - npath)] = beta_plus_scaled<T, Y>(bv[cc], sv[cc], extrapolate(val[cc], yv[cc], sh.cn));
+    }
+    if (npath <= 0 && C == CH) {
+      // wave-uniform: a full chunk of the chain's own nodes (all owned here,
+      // none an ancestor): no per-node test before the stores
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) {
+        const uint32_t n = (uint32_t)(-1 - chunk_code(cl, cc));
+        if (x.write_z) z[n * W + nx + j] = uv[cc];
+        ynew[n * D + 2 * nx + j] = val[cc];
+      }
+      return;
     }
 #pragma unroll
     for (int cc = 0; cc < CH; ++cc) {
